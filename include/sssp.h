@@ -1,0 +1,228 @@
+/*
+ * sssp.h -- C ABI of the MI355X (gfx950) partitioned single-source
+ * shortest-path library: Trishla pruning, asynchronous partitioned solve,
+ * batched solve and the weight gradient of the distances.
+ *
+ * Problem (Sec. I): a directed graph G(V,E) in CSR form, a source s and a
+ * nonnegative cost on every arc; the library computes d(v), the least total
+ * cost of an s->v path, and a shortest-path tree.
+ *
+ * Common conventions
+ *   - Every array argument named "device" is memory on the current HIP
+ *     device; "host" arrays are read during the call only.
+ *   - The caller owns and allocates every buffer, including the workspace.
+ *     The library never allocates or frees device memory during a call.
+ *   - Workspace protocol: call with ws == NULL to have the required size in
+ *     bytes written to *ws_bytes (returns SSSP_OK, enqueues nothing); then
+ *     call again with ws pointing to at least that many bytes (256-byte
+ *     aligned) and *ws_bytes holding its size.
+ *   - All work is enqueued on `stream` (a hipStream_t; NULL = the null
+ *     stream) and the call returns without waiting, unless SSSP_F_SYNC is
+ *     set.  Calls without SSSP_F_SYNC perform no allocation, no host<->device
+ *     copy and no synchronisation, so they may be captured into a HIP graph.
+ *   - Errors found on the host are returned before anything is enqueued.
+ *     Errors found on the device are written to stats->status (when stats is
+ *     non-NULL) and, with SSSP_F_SYNC, returned.
+ *   - Distances: uint32 weights give uint32 distances with 0xFFFFFFFF for
+ *     unreachable vertices; float32 weights give float32 distances with +inf
+ *     for unreachable vertices, accumulated as fl32(d(u) + w) (round to
+ *     nearest even) along the path.
+ *   - Predecessors: pred_edge[v] is the smallest edge id e = (u,v) with
+ *     d(u) + w_e == d(v) (a tight arc), pred[v] its tail u; both are -1 for
+ *     the source and for unreachable vertices.  Edge ids are positions in
+ *     the `col` array of the CSR passed to that call.
+ */
+#ifndef SSSP_H
+#define SSSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- errors */
+enum {
+  SSSP_OK = 0,
+  SSSP_ERR_ARG = -1,          /* null pointer, bad size, bad option        */
+  SSSP_ERR_SOURCE = -2,       /* source outside [0, n)                     */
+  SSSP_ERR_CSR = -3,          /* row_ptr not monotone / != m, col out of range */
+  SSSP_ERR_UNSORTED = -4,     /* sssp_prune: a row is not sorted by column */
+  SSSP_ERR_WEIGHT = -5,       /* fp32 weight negative, -0.0, NaN or inf    */
+  SSSP_ERR_ZERO_WEIGHT = -6,  /* sssp_backward: a weight equal to zero     */
+  SSSP_ERR_OVERFLOW = -7,     /* an integer path sum reached 2^32 - 1, or an
+                                 fp32 path sum overflowed to +inf          */
+  SSSP_ERR_TIMEOUT = -8,      /* max_rounds or the time limit was reached  */
+  SSSP_ERR_WORKSPACE = -9,    /* workspace missing, too small or misaligned */
+  SSSP_ERR_HIP = -10,         /* a HIP runtime call failed                 */
+  SSSP_ERR_CAPTURE = -11,     /* SSSP_F_SYNC requested on a capturing stream */
+  SSSP_ERR_CYCLE = -12        /* sssp_backward: predecessors form a cycle  */
+};
+
+/* Human-readable name of an error code (static string, never NULL). */
+const char *sssp_strerror(int code);
+
+/* ------------------------------------------------------------ the graph */
+enum { SSSP_W_U32 = 0, SSSP_W_F32 = 1 };
+
+typedef struct {
+  int32_t n;              /* number of vertices, n >= 1                    */
+  int32_t m;              /* number of arcs, 0 <= m <= 2^31 - 2            */
+  const int32_t *row_ptr; /* device int32[n+1]: row_ptr[0] = 0, nondecreasing,
+                             row_ptr[n] = m; arcs of u are row_ptr[u]..row_ptr[u+1]-1 */
+  const int32_t *col;     /* device int32[m]: head of every arc, in [0, n)  */
+  const void *w;          /* device uint32[m] or float32[m]: arc costs >= 0 */
+  int32_t wtype;          /* SSSP_W_U32 or SSSP_W_F32                      */
+  int32_t reserved;       /* must be 0                                     */
+} sssp_csr;
+
+/* --------------------------------------------------------------- options */
+enum {
+  SSSP_F_VALIDATE = 1u << 0,     /* check CSR and weights on the device first */
+  SSSP_F_SYNC = 1u << 1,         /* wait for completion, return device status  */
+  SSSP_F_PRUNE_LOCAL = 1u << 2,  /* sssp_prune: LOCAL scope (witness in u's partition) */
+  SSSP_F_NO_AUTOTUNE = 1u << 3   /* never consult the autotune cache           */
+};
+
+typedef struct {
+  double delta;            /* bucket width (distance units); 0 = auto;
+                              < 0 or +inf = one unbounded bucket          */
+  int32_t num_partitions;  /* P, 1D blocks of ceil(n/P) vertices; 0 = auto */
+  int32_t wg_size;         /* threads per workgroup: 256, 512 or 1024; 0 = auto */
+  int32_t num_workgroups;  /* persistent grid size; 0 = auto               */
+  int32_t max_rounds;      /* > 0: stop after this many frontier batches per
+                              workgroup and report SSSP_ERR_TIMEOUT; the
+                              labels are then valid upper bounds           */
+  uint32_t flags;          /* SSSP_F_* */
+  int32_t reserved;        /* must be 0 */
+  void *event_start;       /* optional hipEvent_t recorded right before the
+                              main kernel of the call (NULL = none)        */
+  void *event_stop;        /* optional hipEvent_t recorded right after it  */
+} sssp_opts;
+
+/* Fill *o with the defaults (everything automatic). */
+void sssp_opts_init(sssp_opts *o);
+
+/* --------------------------------------------------------------- stats */
+/* Device-resident counters, optional (NULL = not collected).  The library
+ * zeroes the struct at the start of each call. */
+typedef struct {
+  int32_t status;            /* SSSP_OK or a device-detected SSSP_ERR_*    */
+  int32_t num_partitions;    /* P actually used                            */
+  uint64_t delta_bits;       /* bucket width used (integer, or fp32 bits)  */
+  uint64_t edges_relaxed;    /* arcs examined by the solve                 */
+  uint64_t label_updates;    /* atomic min operations that lowered d(v)   */
+  uint64_t cross_updates;    /* of those, arcs into another partition     */
+  uint64_t vertices_expanded;/* frontier vertices processed (with repeats) */
+  uint64_t batches;          /* frontier batches (bucket rounds)          */
+  uint64_t edges_pruned;     /* sssp_prune: arcs deleted                   */
+  uint64_t wedges;           /* sssp_prune: two-arc paths examined         */
+  uint64_t reserved[6];
+} sssp_stats;
+
+/* --------------------------------------------------------------- prune */
+/*
+ * Trishla (Sec. III-B, Alg. 1): delete every arc e = (u,x,W) for which some
+ * middle vertex y, y != u and y != x, has arcs (u,y,w1) and (y,x,w2) with
+ * w1 + w2 < W (strict; integer sums in 64 bits, fp32 sums compared exactly).
+ * All arcs are tested against the input graph at once.  Scope GLOBAL
+ * (default) allows any y; SSSP_F_PRUNE_LOCAL requires y to lie in u's 1D
+ * partition (Sec. III-A).  Deleting such arcs never changes a distance nor
+ * the predecessor rule's choice (a deleted arc is never tight).
+ *
+ * Requires every row sorted by column (nondecreasing).
+ *   keep            device uint8[m]: 1 = kept, 0 = deleted              (out)
+ *   out_row_ptr     device int32[n+1] or NULL: CSR of the kept arcs    (out)
+ *   out_col, out_w  device int32[m], device uint32/float32[m], or NULL (out)
+ *   edge_map        device int32[m] or NULL: original id of kept arc i (out)
+ * Kept arcs stay in their original order; the kept count is
+ * out_row_ptr[n].  The out_* arrays and edge_map must be all NULL or all set.
+ */
+int sssp_prune(const sssp_csr *g, const sssp_opts *o, uint8_t *keep,
+               int32_t *out_row_ptr, int32_t *out_col, void *out_w,
+               int32_t *edge_map, sssp_stats *stats, void *ws,
+               size_t *ws_bytes, void *stream);
+
+/* --------------------------------------------------------------- solve */
+/*
+ * Single-source shortest paths (Sec. III-C, Alg. 2 and 3) over 1D vertex
+ * partitions (Sec. III-A).  Each partition settles its vertices in order of
+ * delta-wide distance buckets (lowest non-empty bucket first); arcs into
+ * other partitions are relaxed immediately with a 64-bit atomic minimum on
+ * the packed (distance, edge id) label of the head and mark the head in its
+ * owner's inbox -- the asynchronous Bellman-Ford exchange between
+ * partitions.  A device-wide count of pending work replaces the paper's
+ * termination detection (Sec. III-D): the solve ends when it reaches zero.
+ * The result does not depend on delta, P, the grid or the schedule.
+ *   dist        device uint32[n] or float32[n] (per g->wtype)          (out)
+ *   pred        device int32[n] or NULL                                (out)
+ *   pred_edge   device int32[n] or NULL                                (out)
+ */
+int sssp_solve(const sssp_csr *g, int32_t source, const sssp_opts *o,
+               void *dist, int32_t *pred, int32_t *pred_edge,
+               sssp_stats *stats, void *ws, size_t *ws_bytes, void *stream);
+
+/* ---------------------------------------------------------- batched solve */
+/*
+ * Many independent solves in one persistent launch.  Solve i runs on graph
+ * solve_graph[i] (an index into `graphs`) from solve_source[i] and writes
+ * its n_i outputs at element offset out_offset[i] of dist / pred /
+ * pred_edge.  Each solve's result equals sssp_solve on the same input.
+ *   graphs        host sssp_csr[num_graphs] (device pointers inside)
+ *   solve_graph, solve_source   host int32[num_solves]
+ *   out_offset    host int64[num_solves]
+ *   dist          device uint32/float32[total], pred / pred_edge device
+ *                 int32[total] or NULL
+ * All graphs must share one wtype.  The task table is passed to the device
+ * inside kernel arguments, so a captured call replays without the host
+ * arrays.  opts->num_partitions applies per graph (0 = auto per graph).
+ */
+int sssp_solve_batch(int32_t num_graphs, const sssp_csr *graphs,
+                     int32_t num_solves, const int32_t *solve_graph,
+                     const int32_t *solve_source, const int64_t *out_offset,
+                     const sssp_opts *o, void *dist, int32_t *pred,
+                     int32_t *pred_edge, sssp_stats *stats, void *ws,
+                     size_t *ws_bytes, void *stream);
+
+/* ------------------------------------------------------------ backward */
+/*
+ * Gradient of L = sum_v grad_dist[v] * d(v) with respect to every arc cost,
+ * for fp32 graphs (not in the paper).  d(t) is the sum of the costs on the
+ * tree path s -> t, so grad_w[e] = sum of grad_dist[t] over the vertices t
+ * whose tree path uses e: for e = pred_edge[v] it is the total of
+ * grad_dist over the subtree under v, and 0 for every other arc.  Subtree
+ * totals are accumulated in reverse distance order (children before their
+ * parent) in float64 and rounded once to float32.
+ * Requires every weight > 0 (else SSSP_ERR_ZERO_WEIGHT, checked with
+ * SSSP_F_VALIDATE); a predecessor cycle is reported as SSSP_ERR_CYCLE.
+ *   dist, pred_edge   device float32[n], int32[n]: the output of sssp_solve
+ *   grad_dist         device float32[n] (entries of unreachable v ignored)
+ *   grad_w            device float32[m]                                (out)
+ */
+int sssp_backward(const sssp_csr *g, int32_t source, const float *dist,
+                  const int32_t *pred_edge, const float *grad_dist,
+                  float *grad_w, const sssp_opts *o, sssp_stats *stats,
+                  void *ws, size_t *ws_bytes, void *stream);
+
+/* ------------------------------------------------------------ autotune */
+/*
+ * Time candidate (delta, num_partitions, wg_size) settings for sssp_solve on
+ * this graph and source and write the fastest into *best (synchronous; not
+ * for capture).  Results are cached in the process, keyed by the device and
+ * a signature of the graph (n, m, wtype, degree and weight statistics), and
+ * sssp_solve with automatic options consults the cache.  If cache_path is
+ * non-NULL the cache is loaded from and saved to that JSON file.
+ *   dist_scratch  device buffer of 4*n bytes used as the dist output
+ */
+int sssp_autotune(const sssp_csr *g, int32_t source, void *dist_scratch,
+                  sssp_opts *best, const char *cache_path, void *ws,
+                  size_t *ws_bytes, void *stream);
+
+/* Library version string. */
+const char *sssp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SSSP_H */

@@ -1,0 +1,175 @@
+// internal.hpp -- device helpers and launch descriptors shared by the
+// library's kernels (gfx950, wave64).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sssp.h"
+
+namespace sssp_impl {
+
+constexpr int WAVE = 64;
+constexpr uint32_t NONE_EDGE = 0xFFFFFFFFu;
+constexpr unsigned long long LABEL_INF = ~0ull;
+constexpr unsigned long long DELTA_INF = ~0ull;
+
+// ------------------------------------------------------------ atomics
+// Every datum that several workgroups write or read while a kernel runs is
+// accessed with agent-scope atomics: the eight XCDs have private L2 caches,
+// so plain loads could observe stale lines.
+template <typename T>
+__device__ __forceinline__ T ld_acq(const T *p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T ld_rlx(const T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_rlx(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_rel(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T amin(T *p, T v) {
+  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T amax(T *p, T v) {
+  return __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T aadd(T *p, T v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T aor(T *p, T v) {
+  return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T aand_acq(T *p, T v) {
+  return __hip_atomic_fetch_and(p, v, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void set_status(int32_t *st, int32_t code) {
+  int32_t expect = 0;
+  __hip_atomic_compare_exchange_strong(st, &expect, code, __ATOMIC_RELAXED,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------------ wave / block
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, WAVE);
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_min(T x) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    T y = __shfl_xor(x, o, WAVE);
+    x = y < x ? y : x;
+  }
+  return x;
+}
+
+__device__ __forceinline__ int wave_incl_scan(int x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    int y = __shfl_up(x, o, WAVE);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+// Exclusive scan of one int per thread over the block.  `ws` holds
+// BS/64 + 1 ints of LDS.  Returns the exclusive prefix; *total = block sum.
+template <int BS>
+__device__ __forceinline__ int block_excl_scan(int x, int *ws, int *total) {
+  constexpr int NW = BS / WAVE;
+  const int wid = threadIdx.x / WAVE;
+  int incl = wave_incl_scan(x);
+  if (lane_id() == WAVE - 1) ws[wid] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+#pragma unroll
+    for (int i = 0; i < NW; i++) {
+      int t = ws[i];
+      ws[i] = acc;
+      acc += t;
+    }
+    ws[NW] = acc;
+  }
+  __syncthreads();
+  int r = ws[wid] + incl - x;
+  *total = ws[NW];
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------ solve descriptors
+// One independent single-source problem of a (possibly batched) solve.
+struct SolveDesc {
+  const int32_t *row_ptr;
+  const int32_t *col;
+  const uint32_t *w;           // raw 32-bit weights (uint32 or float32 bits)
+  unsigned long long *label;   // n packed labels: dist bits << 32 | edge id
+  uint32_t *dirty;             // ceil(n/32) words: the partitions' inboxes
+  void *dist;                  // outputs, already offset for this solve
+  int32_t *pred;
+  int32_t *pred_edge;
+  unsigned long long delta;    // bucket width in dist units, DELTA_INF = none
+  int32_t n, m, source;
+  int32_t nparts, bsize;       // P and the 1D block size ceil(n/P)
+  int32_t unit0;               // first scheduling unit (partition) index
+  int32_t nwords;              // ceil(n/32)
+  int32_t pad;
+};
+
+// Device-wide control block living in the workspace.
+struct Ctrl {
+  long long work;   // pending work: inbox bits + claimed vertices (+ slack)
+  uint32_t done;    // set once the solve has finished or aborted
+  int32_t status;   // first device-detected error
+  uint32_t nunits;
+  uint32_t pad[11];
+};
+
+// Kernel arguments of the persistent solve.
+struct SolveArgs {
+  const SolveDesc *desc;       // num_solves descriptors
+  int32_t *unit_solve;         // unit -> solve index
+  unsigned long long *thresh;  // per unit: exclusive end of its current bucket
+  uint32_t *abits;             // active-unit bitmap
+  Ctrl *ctrl;
+  sssp_stats *stats;
+  int32_t nunits, nabw;        // units, words of abits
+  int32_t max_rounds;
+  int32_t num_solves;
+  unsigned long long time_limit;  // wall-clock ticks
+};
+
+// Descriptors travel to the device inside kernel arguments (below 4 KiB).
+struct DescChunk {
+  int32_t first, count;
+  SolveDesc d[32];
+};
+
+__device__ __forceinline__ void stat_add(uint64_t *p, uint64_t v) {
+  __hip_atomic_fetch_add(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v,
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace sssp_impl

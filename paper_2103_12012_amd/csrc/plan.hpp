@@ -1,0 +1,34 @@
+// plan.hpp -- host-side helpers shared by the entry points.
+#pragma once
+#include "internal.hpp"
+
+namespace sssp_impl {
+
+struct DevInfo {
+  int cus = 0;
+  int wall_khz = 0;
+};
+
+// Parameters of one solve after defaults and the autotune cache are applied.
+struct SolvePlan {
+  int nparts = 1, bsize = 1;  // P (non-empty blocks) and block size ceil(n/P)
+  int bs = 256, grid = 1;     // workgroup size and persistent grid
+  unsigned long long delta = DELTA_INF;
+};
+
+DevInfo device_info();
+const char *strerror_impl(int code);
+int check_csr(const sssp_csr *g);
+int check_opts(const sssp_opts *o);
+int check_ws(void *ws, size_t have, size_t need);
+int check_sync(const sssp_opts &o, hipStream_t st);
+int finish_sync(const int32_t *dev_status, hipStream_t st);
+SolvePlan make_plan(const sssp_csr &g, const sssp_opts &o);
+unsigned long long delta_units(double delta, int wtype);
+int default_parts(int n);
+double default_delta(int wtype);
+
+// autotune.hip: cached best options for graphs of this signature, if any.
+bool autotune_lookup(const sssp_csr &g, sssp_opts *out);
+
+}  // namespace sssp_impl

@@ -1,0 +1,106 @@
+"""GPU parity of sssp_prune (Trishla) against the oracle: bit-exact keep
+masks (GLOBAL and LOCAL scope, uint32 and fp32 costs), stable compaction
+with the edge map, and the invariant that solving the pruned graph gives the
+same distances and predecessors."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2103_12012_amd import gen
+from helpers import assert_solve_parity, dev, gpu_solve, sssp_mod, tiny_graph
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_keep(g, **kw):
+    rp, c, w = dev(g)
+    keep = sssp_mod().prune(rp, c, w, compact=False, **kw)
+    return keep.cpu().numpy()
+
+
+def test_golden_keep_masks():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "worked_example.json")) as f:
+        gj = json.load(f)
+    e = np.array(gj["edges_u_v_w"])
+    g = gen.from_arcs(gj["n"], e[:, 0], e[:, 1], e[:, 2].astype(np.uint32))
+    assert gpu_keep(g).tolist() == gj["trishla_keep_global"]
+    assert gpu_keep(g, local=True, num_partitions=2).tolist() == gj["trishla_keep_local_p2"]
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_tiny_keep_masks(seed):
+    g = tiny_graph(100 + seed, wmax=6)
+    ref = oracle.trishla(g.row_ptr, g.col, g.w, method="brute")
+    assert np.array_equal(gpu_keep(g), ref)
+    P = 1 + seed % 5
+    refl = oracle.trishla(g.row_ptr, g.col, g.w, True, P, method="brute")
+    assert np.array_equal(gpu_keep(g, local=True, num_partitions=P), refl)
+
+
+def test_c1_keep_mask_and_compaction():
+    g = gen.uniform(4096, 32768, seed=1)
+    rp, c, w = dev(g)
+    S = sssp_mod()
+    st = S.StatsBuffer.new("cuda")
+    keep, (prp, pc, pw, emap) = S.prune(rp, c, w, num_partitions=4, stats=st)
+    ref = oracle.trishla(g.row_ptr, g.col, g.w)
+    keep = keep.cpu().numpy()
+    assert np.array_equal(keep, ref)
+    kept = np.nonzero(ref)[0]
+    assert np.array_equal(emap.cpu().numpy(), kept)
+    assert np.array_equal(pc.cpu().numpy(), g.col[kept])
+    assert np.array_equal(pw.cpu().numpy().view(np.uint32), g.w[kept])
+    cnt = np.bincount(g.src()[kept], minlength=g.n)
+    assert np.array_equal(prp.cpu().numpy(), np.concatenate([[0], np.cumsum(cnt)]))
+    s = st.read()
+    assert s["status"] == 0 and s["edges_pruned"] == g.m - kept.size and s["wedges"] > 0
+
+
+@pytest.mark.parametrize("scale,seed", [(10, 11), (13, 12), (16, 13)])
+def test_rmat_keep_mask(scale, seed):
+    g = gen.rmat(scale, seed)
+    assert np.array_equal(gpu_keep(g), oracle.trishla(g.row_ptr, g.col, g.w))
+
+
+def test_rmat_local_scope_subset():
+    g = gen.rmat(12, 5)
+    kg = gpu_keep(g)
+    for P in (1, 16, 64):
+        kl = gpu_keep(g, local=True, num_partitions=P)
+        assert np.array_equal(kl, oracle.trishla(g.row_ptr, g.col, g.w, True, P))
+        assert np.all(kl >= kg)
+
+
+def test_fp32_keep_mask():
+    g = gen.rmat(11, 9, weight="f32", wlo=0.5, whi=1.5)
+    assert np.array_equal(gpu_keep(g), oracle.trishla(g.row_ptr, g.col, g.w))
+
+
+def test_grid_prunes_nothing():
+    g = gen.grid(300, 200, seed=3)
+    assert gpu_keep(g).all()
+
+
+@pytest.mark.parametrize("scale,seed", [(12, 31), (15, 32)])
+def test_pruned_solve_equals_unpruned(scale, seed):
+    g = gen.rmat(scale, seed)
+    rp, c, w = dev(g)
+    S = sssp_mod()
+    keep, (prp, pc, pw, emap) = S.prune(rp, c, w)
+    emap = emap.cpu().numpy()
+    for s in gen.random_sources(g, 3, seed):
+        ref = oracle.solve(g.row_ptr, g.col, g.w, int(s))
+        dist, pred, pe = S.solve(prp, pc, pw, int(s))
+        pe = pe.cpu().numpy()
+        pe = np.where(pe >= 0, emap[np.maximum(pe, 0)], -1)
+        assert_solve_parity(g, s, (dist.cpu().numpy().view(np.uint32), pred.cpu().numpy(), pe),
+                            ref)
+
+
+def test_rmat20_keep_mask_full_size():
+    g = gen.rmat(20, 20)
+    assert np.array_equal(gpu_keep(g, num_partitions=256), oracle.trishla(g.row_ptr, g.col, g.w))
