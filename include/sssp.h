@@ -88,14 +88,20 @@ enum {
 typedef struct {
   double delta;            /* bucket width (distance units); 0 = auto;
                               < 0 or +inf = one unbounded bucket          */
-  int32_t num_partitions;  /* P, 1D blocks of ceil(n/P) vertices; 0 = auto */
+  int32_t num_partitions;  /* P, 1D blocks of ceil(n/P) vertices; 0 = auto;
+                              raised so that a block has at most 32768 vertices */
   int32_t wg_size;         /* threads per workgroup: 256, 512 or 1024; 0 = auto */
   int32_t num_workgroups;  /* persistent grid size; 0 = auto               */
   int32_t max_rounds;      /* > 0: stop after this many frontier batches per
                               workgroup and report SSSP_ERR_TIMEOUT; the
                               labels are then valid upper bounds           */
   uint32_t flags;          /* SSSP_F_* */
-  int32_t reserved;        /* must be 0 */
+  int32_t lag;             /* sssp_solve: a partition may expand its lowest
+                              bucket only while its pending minimum is within
+                              lag * delta of the least pending distance of the
+                              whole graph; 0 = auto, < 0 = unbounded (fully
+                              asynchronous partitions).  Batched solves are
+                              always unbounded.  Results never depend on it. */
   void *event_start;       /* optional hipEvent_t recorded right before the
                               main kernel of the call (NULL = none)        */
   void *event_stop;        /* optional hipEvent_t recorded right after it  */
@@ -207,12 +213,17 @@ int sssp_backward(const sssp_csr *g, int32_t source, const float *dist,
 
 /* ------------------------------------------------------------ autotune */
 /*
- * Time candidate (delta, num_partitions, wg_size) settings for sssp_solve on
- * this graph and source and write the fastest into *best (synchronous; not
- * for capture).  Results are cached in the process, keyed by the device and
- * a signature of the graph (n, m, wtype, degree and weight statistics), and
- * sssp_solve with automatic options consults the cache.  If cache_path is
- * non-NULL the cache is loaded from and saved to that JSON file.
+ * Time candidate (delta, num_partitions, wg_size, lag) settings for
+ * sssp_solve on this graph and source and write the fastest into *best
+ * (synchronous; not for capture).  *best is in/out: fields the caller sets
+ * to nonzero values (delta, num_partitions, wg_size, num_workgroups, lag)
+ * are kept fixed, the others are searched (delta over multiples of the mean
+ * arc cost sampled from the device, and one unbounded bucket).  Results
+ * are cached in the process, keyed by the device and a signature of the
+ * graph (weight type, ceil(log2 n), rounded log2 of the average degree), and
+ * sssp_solve / sssp_solve_batch with automatic options consult the cache.
+ * If cache_path is non-NULL the cache is loaded from and saved to that JSON
+ * file.
  *   dist_scratch  device buffer of 4*n bytes used as the dist output
  */
 int sssp_autotune(const sssp_csr *g, int32_t source, void *dist_scratch,

@@ -64,7 +64,6 @@ int check_csr(const sssp_csr *g) {
 }
 
 int check_opts(const sssp_opts *o) {
-  if (o->reserved != 0) return SSSP_ERR_ARG;
   if (o->wg_size != 0 && o->wg_size != 256 && o->wg_size != 512 && o->wg_size != 1024)
     return SSSP_ERR_ARG;
   if (o->num_partitions < 0 || o->num_workgroups < 0 || o->max_rounds < 0) return SSSP_ERR_ARG;
@@ -125,7 +124,7 @@ SolvePlan make_plan(const sssp_csr &g, const sssp_opts &o) {
   sssp_opts tuned;
   bool have = false;
   if (!(o.flags & SSSP_F_NO_AUTOTUNE) &&
-      (o.delta == 0 || o.num_partitions == 0 || o.wg_size == 0))
+      (o.delta == 0 || o.num_partitions == 0 || o.wg_size == 0 || o.lag == 0))
     have = autotune_lookup(g, &tuned);
   double delta = o.delta != 0 ? o.delta : (have && tuned.delta != 0 ? tuned.delta
                                                                      : default_delta(g.wtype));
@@ -133,12 +132,15 @@ SolvePlan make_plan(const sssp_csr &g, const sssp_opts &o) {
                                : (have && tuned.num_partitions > 0 ? tuned.num_partitions
                                                                    : default_parts(g.n));
   if (P > g.n) P = g.n;
+  const int pmin = (int)(((long long)g.n + 32767) / 32768);  // blocks <= 32768 vertices
+  if (P < pmin) P = pmin;
   pl.bsize = (g.n + P - 1) / P;
   pl.nparts = (g.n + pl.bsize - 1) / pl.bsize;  // non-empty blocks only
   pl.delta = delta_units(delta, g.wtype);
   pl.bs = o.wg_size ? o.wg_size : (have && tuned.wg_size ? tuned.wg_size : 256);
   pl.grid = o.num_workgroups ? o.num_workgroups
                              : (have && tuned.num_workgroups ? tuned.num_workgroups : 0);
+  pl.lag = o.lag ? o.lag : (have ? tuned.lag : 0);
   return pl;
 }
 
@@ -148,14 +150,14 @@ int plan_grid(int wtype, int bs, int want) {
   const DevInfo di = device_info();
   const int per_cu = solve_max_blocks_per_cu(wtype, bs);
   const int resident = di.cus * per_cu;
-  if (want <= 0) want = di.cus * (per_cu < 2 ? per_cu : 2);
+  if (want <= 0) want = resident;
   int grid = want < resident ? want : resident;
   return grid < 1 ? 1 : grid;
 }
 
 // Workspace layout of a (batched) solve.
 struct SolveLayout {
-  size_t desc = 0, unit_solve = 0, thresh = 0, abits = 0, ctrl = 0, total = 0;
+  size_t desc = 0, unit_solve = 0, unit_min = 0, abits = 0, ctrl = 0, total = 0;
   std::vector<size_t> label, dirty;
 };
 
@@ -171,7 +173,7 @@ SolveLayout solve_layout(int nsolves, const std::vector<int> &ns, int nunits) {
   L.ctrl = take(sizeof(Ctrl));
   L.desc = take(sizeof(SolveDesc) * (size_t)nsolves);
   L.unit_solve = take(sizeof(int32_t) * (size_t)nunits);
-  L.thresh = take(sizeof(unsigned long long) * (size_t)nunits);
+  L.unit_min = take(sizeof(unsigned long long) * (size_t)nunits);
   L.abits = take(sizeof(uint32_t) * (size_t)nabw);
   L.label.resize(nsolves);
   L.dirty.resize(nsolves);
@@ -182,6 +184,23 @@ SolveLayout solve_layout(int nsolves, const std::vector<int> &ns, int nunits) {
   L.total = off;
   return L;
 }
+
+// lag * delta in distance units: an integer, or the fp32 bits of lag * delta.
+unsigned long long window_units(unsigned long long delta, unsigned long long lag, int wtype) {
+  if (wtype == SSSP_W_U32) {
+    const unsigned long long w = delta * lag;
+    return w / lag == delta ? w : DELTA_INF;
+  }
+  float d;
+  uint32_t b = (uint32_t)delta;
+  std::memcpy(&d, &b, 4);
+  const float w = d * (float)lag;
+  uint32_t wb;
+  std::memcpy(&wb, &w, 4);
+  return wb;
+}
+
+thread_local double g_solve_time_limit_s = 30.0;
 
 unsigned long long time_limit_ticks(double seconds) {
   return (unsigned long long)(seconds * (double)device_info().wall_khz * 1000.0);
@@ -195,7 +214,7 @@ int run_solves(std::vector<SolveDesc> &descs, const SolveLayout &L, int nunits, 
   std::memset(&a, 0, sizeof(a));
   a.desc = reinterpret_cast<const SolveDesc *>(ws + L.desc);
   a.unit_solve = reinterpret_cast<int32_t *>(ws + L.unit_solve);
-  a.thresh = reinterpret_cast<unsigned long long *>(ws + L.thresh);
+  a.unit_min = reinterpret_cast<unsigned long long *>(ws + L.unit_min);
   a.abits = reinterpret_cast<uint32_t *>(ws + L.abits);
   a.ctrl = reinterpret_cast<Ctrl *>(ws + L.ctrl);
   a.stats = stats;
@@ -203,7 +222,12 @@ int run_solves(std::vector<SolveDesc> &descs, const SolveLayout &L, int nunits, 
   a.nabw = (nunits + 31) / 32;
   a.max_rounds = o.max_rounds;
   a.num_solves = (int)descs.size();
-  a.time_limit = time_limit_ticks(10.0);
+  a.window = DELTA_INF;
+  if (descs.size() == 1 && o.lag >= 0 && descs[0].delta != DELTA_INF) {
+    const unsigned long long lag = o.lag > 0 ? (unsigned long long)o.lag : 2ull;
+    a.window = window_units(descs[0].delta, lag, wtype);
+  }
+  a.time_limit = time_limit_ticks(g_solve_time_limit_s);
 
   const int ns = (int)descs.size();
   int max_n = 1;
@@ -285,6 +309,7 @@ extern "C" int sssp_solve(const sssp_csr *g, int32_t source, const sssp_opts *o,
   d.bsize = pl.bsize;
   d.unit0 = 0;
   d.nwords = (g->n + 31) / 32;
+  opts.lag = pl.lag;
   return run_solves(descs, L, pl.nparts, g->wtype, pl.bs, plan_grid(g->wtype, pl.bs, pl.grid),
                     opts, g, 1, stats, w, st);
 }
@@ -394,14 +419,11 @@ extern "C" int sssp_prune(const sssp_csr *g, const sssp_opts *o, uint8_t *keep,
   const int bsize = (g->n + P - 1) / P;
   const int local = (opts.flags & SSSP_F_PRUNE_LOCAL) ? 1 : 0;
   int32_t *dev_status = nullptr;
-  if (opts.event_start && hipEventRecord((hipEvent_t)opts.event_start, st) != hipSuccess)
-    return SSSP_ERR_HIP;
   rc = launch_prune(*g, local, bsize, keep, out_row_ptr, out_col, out_w, edge_map, stats,
                     static_cast<char *>(ws), device_info().cus,
-                    (opts.flags & SSSP_F_VALIDATE) != 0, &dev_status, st);
+                    (opts.flags & SSSP_F_VALIDATE) != 0, opts.event_start, opts.event_stop,
+                    &dev_status, st);
   if (rc) return rc;
-  if (opts.event_stop && hipEventRecord((hipEvent_t)opts.event_stop, st) != hipSuccess)
-    return SSSP_ERR_HIP;
   if (opts.flags & SSSP_F_SYNC) return finish_sync(dev_status, st);
   return SSSP_OK;
 }

@@ -5,8 +5,8 @@
 // describes for delta-stepping: a wide bucket exposes more parallel work per
 // round but re-relaxes more vertices, a narrow one needs more rounds.  The
 // candidates are multiples of the mean arc cost (sampled from the device).
-// Results are cached per (device, n, m, weight type) in the process and can
-// be persisted as JSON; sssp_solve with automatic options consults the cache.
+// Results are cached per device and coarse graph signature in the process and
+// can be persisted as JSON; solves with automatic options consult the cache.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -26,18 +26,28 @@ namespace {
 std::mutex g_mu;
 std::map<std::string, sssp_opts> g_cache;
 
+// "<arch>/<CUs>" of the current device (queried once per device).
 std::string device_tag() {
+  static std::map<int, std::string> tags;  // guarded by g_mu
   int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+  auto it = tags.find(dev);
+  if (it != tags.end()) return it->second;
   hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
-    return "unknown";
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
   std::string arch = prop.gcnArchName;
-  return arch + "/" + std::to_string(prop.multiProcessorCount);
+  return tags[dev] = arch + "/" + std::to_string(prop.multiProcessorCount);
 }
 
+// Coarse signature: graphs of the same weight type, the same ceil(log2 n)
+// and a similar average degree share an entry.
 std::string graph_key(const sssp_csr &g) {
-  return device_tag() + "|n=" + std::to_string(g.n) + "|m=" + std::to_string(g.m) +
-         "|w=" + std::to_string(g.wtype);
+  int ln = 0;
+  while ((1ll << ln) < (long long)g.n) ln++;
+  const double avg = g.m > 0 ? (double)g.m / g.n : 0.0;
+  const int ld = avg > 0 ? (int)std::lround(4.0 * std::log2(avg)) : -99;
+  return device_tag() + "|w=" + std::to_string(g.wtype) + "|log2n=" + std::to_string(ln) +
+         "|4log2deg=" + std::to_string(ld);
 }
 
 void load_json(const char *path) {
@@ -49,7 +59,7 @@ void load_json(const char *path) {
   while ((k = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, k);
   std::fclose(f);
   // one entry per line: {"key": "...", "delta": D, "num_partitions": P,
-  //                      "wg_size": W, "num_workgroups": G}
+  //                      "wg_size": W, "num_workgroups": G, "lag": L}
   size_t pos = 0;
   while ((pos = text.find("{\"key\": \"", pos)) != std::string::npos) {
     const size_t ks = pos + 9;
@@ -57,17 +67,18 @@ void load_json(const char *path) {
     if (ke == std::string::npos) break;
     const std::string key = text.substr(ks, ke - ks);
     double delta = 0;
-    int P = 0, W = 0, G = 0;
+    int P = 0, W = 0, G = 0, Lg = 0;
     if (std::sscanf(text.c_str() + ke + 1,
                     ", \"delta\": %lf, \"num_partitions\": %d, \"wg_size\": %d, "
-                    "\"num_workgroups\": %d",
-                    &delta, &P, &W, &G) == 4) {
+                    "\"num_workgroups\": %d, \"lag\": %d",
+                    &delta, &P, &W, &G, &Lg) == 5) {
       sssp_opts o;
       std::memset(&o, 0, sizeof(o));
       o.delta = delta;
       o.num_partitions = P;
       o.wg_size = W;
       o.num_workgroups = G;
+      o.lag = Lg;
       g_cache[key] = o;
     }
     pos = ke;
@@ -83,9 +94,9 @@ void save_json(const char *path) {
     const sssp_opts &o = kv.second;
     std::fprintf(f,
                  "{\"key\": \"%s\", \"delta\": %.17g, \"num_partitions\": %d, \"wg_size\": %d, "
-                 "\"num_workgroups\": %d}%s\n",
+                 "\"num_workgroups\": %d, \"lag\": %d}%s\n",
                  kv.first.c_str(), o.delta, o.num_partitions, o.wg_size, o.num_workgroups,
-                 ++i < g_cache.size() ? "," : "");
+                 o.lag, ++i < g_cache.size() ? "," : "");
   }
   std::fprintf(f, "]\n");
   std::fclose(f);
@@ -93,26 +104,42 @@ void save_json(const char *path) {
 
 struct Candidate {
   double delta;
-  int parts, wg, grid;
+  int parts, wg, lag;
 };
 
-std::vector<Candidate> candidates(const sssp_csr &g, double mean_w) {
-  const int cus = device_info().cus;
+// Candidates around the defaults; fields the caller fixed in *best are kept.
+std::vector<Candidate> candidates(const sssp_csr &g, double mean_w, const sssp_opts &fixed) {
   std::vector<double> deltas;
-  for (double f : {0.25, 1.0, 4.0, 16.0}) deltas.push_back(mean_w * f);
-  deltas.push_back(-1.0);  // one unbounded bucket: asynchronous Bellman-Ford
-  std::vector<int> parts;
-  const int p0 = default_parts(g.n);
-  for (int p : {p0 / 4, p0, p0 * 4}) {
-    int q = std::max(1, std::min(p, g.n));
-    if (std::find(parts.begin(), parts.end(), q) == parts.end()) parts.push_back(q);
+  if (fixed.delta != 0) {
+    deltas.push_back(fixed.delta);
+  } else {
+    for (double f : {0.25, 0.5, 1.0, 2.0, 8.0, 32.0}) deltas.push_back(mean_w * f);
+    deltas.push_back(-1.0);  // one unbounded bucket: asynchronous Bellman-Ford
   }
+  std::vector<int> parts;
+  if (fixed.num_partitions > 0) {
+    parts.push_back(fixed.num_partitions);
+  } else {
+    const int p0 = default_parts(g.n);
+    for (int p : {p0 / 4, p0, p0 * 4}) {
+      int q = std::max(1, std::min(p, g.n));
+      if (std::find(parts.begin(), parts.end(), q) == parts.end()) parts.push_back(q);
+    }
+  }
+  std::vector<int> wgs;
+  if (fixed.wg_size) wgs.push_back(fixed.wg_size);
+  else wgs = {256, 512};
+  std::vector<int> lags;
+  if (fixed.lag) lags.push_back(fixed.lag);
+  else lags = {1, 2, -1};
   std::vector<Candidate> out;
   for (double d : deltas)
-    for (int p : parts) {
-      out.push_back({d, p, 256, 2 * cus});
-      out.push_back({d, p, 512, 2 * cus});
-    }
+    for (int p : parts)
+      for (int w : wgs)
+        for (int l : lags) {
+          if (d < 0 && l != lags[0]) continue;  // no window without buckets
+          out.push_back({d, p, w, l});
+        }
   return out;
 }
 }  // namespace
@@ -140,7 +167,7 @@ extern "C" int sssp_autotune(const sssp_csr *g, int32_t source, void *dist_scrat
   // workspace: the largest requirement over the candidate partition counts
   size_t need = 0;
   {
-    const int p0 = default_parts(g->n);
+    const int p0 = best->num_partitions > 0 ? best->num_partitions : default_parts(g->n);
     for (int p : {p0 / 4, p0, p0 * 4}) {
       sssp_opts o;
       sssp_opts_init(&o);
@@ -193,13 +220,20 @@ extern "C" int sssp_autotune(const sssp_csr *g, int32_t source, void *dist_scrat
   sssp_opts best_o;
   sssp_opts_init(&best_o);
   bool found = false;
-  for (const Candidate &c : candidates(*g, mean_w)) {
+  const sssp_opts fixed = *best;
+  struct LimitGuard {
+    ~LimitGuard() { g_solve_time_limit_s = 30.0; }
+  } guard;
+  for (const Candidate &c : candidates(*g, mean_w, fixed)) {
+    // a candidate slower than 4x the best so far stops at the time limit
+    g_solve_time_limit_s = found ? std::min(30.0, std::max(0.02, 4e-3 * best_ms)) : 30.0;
     sssp_opts o;
     sssp_opts_init(&o);
     o.delta = c.delta;
     o.num_partitions = c.parts;
     o.wg_size = c.wg;
-    o.num_workgroups = c.grid;
+    o.lag = c.lag;
+    o.num_workgroups = fixed.num_workgroups;
     o.flags = SSSP_F_NO_AUTOTUNE;
     o.event_start = e0;
     o.event_stop = e1;
@@ -209,9 +243,15 @@ extern "C" int sssp_autotune(const sssp_csr *g, int32_t source, void *dist_scrat
       size_t b = *ws_bytes;
       o.flags = SSSP_F_NO_AUTOTUNE | SSSP_F_SYNC;
       rc = sssp_solve(g, source, &o, dist_scratch, nullptr, nullptr, nullptr, ws, &b, stream);
-      if (rc != SSSP_OK) {
+      if (rc == SSSP_ERR_TIMEOUT && found) {  // slower than the best: skip it
+        rc = SSSP_OK;
         ok = false;
         break;
+      }
+      if (rc != SSSP_OK) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return rc;
       }
       float ms = 0;
       if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
@@ -228,7 +268,7 @@ extern "C" int sssp_autotune(const sssp_csr *g, int32_t source, void *dist_scrat
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (!found) return rc ? rc : SSSP_ERR_TIMEOUT;
+  if (!found) return SSSP_ERR_TIMEOUT;
   best_o.flags = 0;
   best_o.event_start = nullptr;
   best_o.event_stop = nullptr;

@@ -61,6 +61,36 @@ __device__ __forceinline__ void set_status(int32_t *st, int32_t code) {
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// ------------------------------------------------------------ uniform values
+// Values read from LDS are uniform across the workgroup but the compiler
+// cannot prove it; moving them to scalar registers frees vector registers.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ unsigned long long uni64(unsigned long long x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+template <typename T>
+__device__ __forceinline__ T *uni_ptr(T *p) {
+  return reinterpret_cast<T *>(uni64(reinterpret_cast<unsigned long long>(p)));
+}
+
+// Hides a uniform pointer's value from the optimiser (no instruction is
+// emitted), so addresses derived from it inside a persistent loop are
+// recomputed each iteration instead of being hoisted and kept live.
+template <typename T>
+__device__ __forceinline__ T *opaque(T *p) {
+  unsigned long long x = reinterpret_cast<unsigned long long>(p);
+  asm volatile("" : "+s"(x));
+  return reinterpret_cast<T *>(x);
+}
+
+// Same for a per-lane value (e.g. the thread index) inside a persistent loop.
+__device__ __forceinline__ int opaque_v(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 // ------------------------------------------------------------ wave / block
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
 
@@ -149,13 +179,14 @@ struct Ctrl {
 struct SolveArgs {
   const SolveDesc *desc;       // num_solves descriptors
   int32_t *unit_solve;         // unit -> solve index
-  unsigned long long *thresh;  // per unit: exclusive end of its current bucket
+  unsigned long long *unit_min;  // per unit: least pending distance (lower bound)
   uint32_t *abits;             // active-unit bitmap
   Ctrl *ctrl;
   sssp_stats *stats;
   int32_t nunits, nabw;        // units, words of abits
   int32_t max_rounds;
   int32_t num_solves;
+  unsigned long long window;      // bounded lag in dist units (DELTA_INF = none)
   unsigned long long time_limit;  // wall-clock ticks
 };
 

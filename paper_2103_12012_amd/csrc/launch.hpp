@@ -19,13 +19,15 @@ __global__ void k_copy_status(const int32_t *status, sssp_stats *stats);
 size_t scan_tmp_bytes(int n);
 hipError_t launch_excl_scan(const int32_t *in, int n, int32_t *out, int32_t *tmp,
                             hipStream_t st);
+hipError_t launch_excl_scan_u8(const uint8_t *in, int n, int32_t *out, int32_t *tmp,
+                               hipStream_t st);
 
 // prune.hip
 size_t prune_ws_bytes(int n, int m, bool compact);
 int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t *out_row_ptr,
                  int32_t *out_col, void *out_w, int32_t *edge_map, sssp_stats *stats,
-                 char *ws, int grid_cus, bool validate, int32_t **status_out,
-                 hipStream_t st);
+                 char *ws, int grid_cus, bool validate, void *ev_start, void *ev_stop,
+                 int32_t **status_out, hipStream_t st);
 
 // backward.hip
 size_t backward_ws_bytes(int n);

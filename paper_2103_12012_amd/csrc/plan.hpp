@@ -14,6 +14,7 @@ struct SolvePlan {
   int nparts = 1, bsize = 1;  // P (non-empty blocks) and block size ceil(n/P)
   int bs = 256, grid = 1;     // workgroup size and persistent grid
   unsigned long long delta = DELTA_INF;
+  int lag = 0;                // window in buckets (0 = default)
 };
 
 DevInfo device_info();
@@ -27,6 +28,10 @@ SolvePlan make_plan(const sssp_csr &g, const sssp_opts &o);
 unsigned long long delta_units(double delta, int wtype);
 int default_parts(int n);
 double default_delta(int wtype);
+
+// Device time limit of one solve launch in seconds (per host thread);
+// sssp_autotune lowers it so that a slow candidate ends early.
+extern thread_local double g_solve_time_limit_s;
 
 // autotune.hip: cached best options for graphs of this signature, if any.
 bool autotune_lookup(const sssp_csr &g, sssp_opts *out);

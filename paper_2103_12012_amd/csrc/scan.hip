@@ -10,7 +10,8 @@ constexpr int SCAN_BS = 256;
 constexpr int SCAN_EPT = 8;
 constexpr int SCAN_TILE = SCAN_BS * SCAN_EPT;
 
-__global__ __launch_bounds__(SCAN_BS) void k_scan_tiles(const int32_t *in, int n, int32_t *out,
+template <typename T>
+__global__ __launch_bounds__(SCAN_BS) void k_scan_tiles(const T *in, int n, int32_t *out,
                                                         int32_t *tile_sum) {
   __shared__ int ws[SCAN_BS / WAVE + 1];
   const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_EPT;
@@ -18,7 +19,7 @@ __global__ __launch_bounds__(SCAN_BS) void k_scan_tiles(const int32_t *in, int n
   int s = 0;
 #pragma unroll
   for (int j = 0; j < SCAN_EPT; j++) {
-    v[j] = base + j < n ? in[base + j] : 0;
+    v[j] = base + j < n ? (int)in[base + j] : 0;
     s += v[j];
   }
   int tot;
@@ -72,15 +73,25 @@ size_t scan_tmp_bytes(int n) {
   return sizeof(int32_t) * (size_t)(ntiles > 0 ? ntiles : 1);
 }
 
-hipError_t launch_excl_scan(const int32_t *in, int n, int32_t *out, int32_t *tmp,
-                            hipStream_t st) {
+template <typename T>
+static hipError_t excl_scan_t(const T *in, int n, int32_t *out, int32_t *tmp, hipStream_t st) {
   const int ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
   if (ntiles > 0)
-    hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(SCAN_BS), 0, st, in, n, out, tmp);
+    hipLaunchKernelGGL(k_scan_tiles<T>, dim3(ntiles), dim3(SCAN_BS), 0, st, in, n, out, tmp);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_BS), 0, st, tmp, ntiles, out + n);
   if (ntiles > 0)
     hipLaunchKernelGGL(k_scan_add, dim3(ntiles), dim3(SCAN_BS), 0, st, out, n, tmp);
   return hipGetLastError();
+}
+
+hipError_t launch_excl_scan(const int32_t *in, int n, int32_t *out, int32_t *tmp,
+                            hipStream_t st) {
+  return excl_scan_t(in, n, out, tmp, st);
+}
+
+hipError_t launch_excl_scan_u8(const uint8_t *in, int n, int32_t *out, int32_t *tmp,
+                               hipStream_t st) {
+  return excl_scan_t(in, n, out, tmp, st);
 }
 
 }  // namespace sssp_impl

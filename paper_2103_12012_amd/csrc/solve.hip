@@ -22,16 +22,25 @@
 //  * Nothing waits on a particular workgroup: any resident workgroup can
 //    take any unit, so the launch needs no co-residency guarantee.  Idle
 //    workgroups poll with backoff under a wall-clock limit.
+#include <climits>
+
 #include "internal.hpp"
 #include "launch.hpp"
 
 namespace sssp_impl {
 
-constexpr int FCAP = 2048;  // frontier vertices staged in LDS per batch
+constexpr int FCAP = 1024;  // frontier vertices staged in LDS per round
+constexpr int MAXB = 32768; // largest partition (vertices)
+constexpr int MAX_ROUNDS_PER_BATCH = 256;
 
 template <int WT> struct Dist;
 template <> struct Dist<SSSP_W_U32> {
   static constexpr uint32_t INF_BITS = 0xFFFFFFFFu;
+  // d <= g + window
+  __device__ static __forceinline__ bool within(unsigned long long d, unsigned long long g,
+                                                unsigned long long window) {
+    return d <= g + window;
+  }
   // d + w in 64 bits; overflow when it reaches the unreachable sentinel.
   __device__ static __forceinline__ uint32_t add(uint32_t d, uint32_t w, bool &ovf) {
     unsigned long long s = (unsigned long long)d + w;
@@ -46,6 +55,13 @@ template <> struct Dist<SSSP_W_U32> {
 };
 template <> struct Dist<SSSP_W_F32> {
   static constexpr uint32_t INF_BITS = 0x7F800000u;
+  // d <= g + window, on the fp32 values (saturated keys count as +inf)
+  __device__ static __forceinline__ bool within(unsigned long long d, unsigned long long g,
+                                                unsigned long long window) {
+    if (d >= 0x7F800000ull) return false;
+    return __uint_as_float((uint32_t)d) <=
+           __uint_as_float((uint32_t)g) + __uint_as_float((uint32_t)window);
+  }
   // fl32(d + w), round to nearest even; +inf counts as overflow.
   __device__ static __forceinline__ uint32_t add(uint32_t d, uint32_t w, bool &ovf) {
     float s = __uint_as_float(d) + __uint_as_float(w);
@@ -96,59 +112,100 @@ __global__ void k_init_global(SolveArgs a, int nsolves) {
 }
 
 // Per-solve init (blockIdx.y = solve): labels to +inf, empty inboxes, unit
-// tables; the source gets label (0, no edge) and its inbox bit.
+// tables; the source gets label (0, no edge) and its inbox bit, and its unit
+// the pending minimum 0.
 __global__ void k_init(SolveArgs a) {
   const int s = blockIdx.y;
   const SolveDesc d = a.desc[s];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int stride = gridDim.x * blockDim.x;
+  const int ps = d.source / d.bsize;
   for (int v = t; v < d.n; v += stride)
     d.label[v] = v == d.source ? (unsigned long long)NONE_EDGE : LABEL_INF;
   for (int i = t; i < d.nwords; i += stride)
     d.dirty[i] = i == (d.source >> 5) ? (1u << (d.source & 31)) : 0u;
   for (int p = t; p < d.nparts; p += stride) {
-    a.thresh[d.unit0 + p] = d.delta;  // end of bucket 0
+    a.unit_min[d.unit0 + p] = p == ps ? 0ull : LABEL_INF;
     a.unit_solve[d.unit0 + p] = s;
   }
   if (t == 0) {
-    const int u = d.unit0 + d.source / d.bsize;
+    const int u = d.unit0 + ps;
     aor(&a.abits[u >> 5], 1u << (u & 31));
   }
 }
 
+// Bijective 32-bit mix of a unit id (per-workgroup key) used to break ties
+// between units of equal pending minimum differently in every workgroup.
+__device__ __forceinline__ uint32_t unit_mix(uint32_t u, uint32_t key) {
+  return (u ^ key) * 0x9E3779B1u;
+}
+__device__ __forceinline__ uint32_t unit_unmix(uint32_t x, uint32_t key) {
+  return (x * 0x0E8B2F51u) ^ key;
+}
+
 // ------------------------------------------------------------------ solve
+//
+// One batch of a workgroup:
+//  1. pick: among active units, the one with the least pending minimum
+//     (best-first over partitions), skipping units more than `window` above
+//     the global least (bounded lag); claim it by clearing its active bit;
+//  2. gather: list the unit's inbox bits (up to FCAP) and load their labels
+//     in parallel; the lowest non-empty bucket [kD, (k+1)D) of the listed
+//     distances is claimed, one atomic and-not per inbox word;
+//  3. stage the claimed vertices' rows and distances in LDS and scan the
+//     degrees;
+//  4. relax edge-parallel, U arcs per thread in flight;
+//  5. settle the pending count, publish the unit's remaining minimum and
+//     reactivate it if it still holds work.
+#ifndef SSSP_SOLVE_MIN_WAVES
+#define SSSP_SOLVE_MIN_WAVES 2
+#endif
 template <int WT, int BS>
-__global__ __launch_bounds__(BS) void k_solve(SolveArgs a) {
-  constexpr int EPT = FCAP / BS;  // frontier entries per thread in staging
+__global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_solve(SolveArgs a) {
   constexpr int NW = BS / WAVE;
+  constexpr int U = 4;  // arcs per thread per round
+  constexpr int EPT = FCAP / BS;
   static_assert(FCAP % BS == 0, "FCAP must be a multiple of the block size");
 
-  __shared__ int32_t s_v[FCAP];      // claimed vertex, or -1 for a hole
-  __shared__ uint32_t s_d[FCAP];     // its distance bits at expansion time
-  __shared__ int32_t s_rs[FCAP];     // its first edge
-  __shared__ int32_t s_off[FCAP + 1];// exclusive prefix of degrees
+  __shared__ int32_t s_v[FCAP];       // claimed frontier vertices
+  __shared__ uint32_t s_d[FCAP];      // gather: listed distances; relax: frontier distances
+  __shared__ int32_t s_rs[FCAP];      // gather: listed vertices;  relax: first arc of each
+  __shared__ int32_t s_off[FCAP + 1]; // gather: near mask per word; relax: degree prefix
   __shared__ int s_ws[NW + 1];
+  __shared__ unsigned long long s_red[NW];
   __shared__ SolveDesc s_desc;
-  __shared__ int s_unit, s_solve, s_cnt, s_left, s_push, s_exit, s_claimed;
-  __shared__ unsigned long long s_min;
+  __shared__ int s_unit, s_solve, s_exit, s_nlist, s_cnt, s_claimed, s_push, s_idle, s_stay;
+  __shared__ unsigned long long s_far, s_lmin, s_gmin;
   __shared__ unsigned int s_upd, s_cross, s_new;
+  __shared__ int32_t s_nv[FCAP];           // next round's frontier (same bucket)
+  __shared__ uint32_t s_mark[MAXB / 32];   // partition-local dedupe of s_nv
+  __shared__ int s_ncnt;
+  __shared__ long long s_tot, s_exp;
 
-  const int tid = threadIdx.x;
+  const int tid0 = threadIdx.x;
+  for (int i = tid0; i < MAXB / 32; i += BS) s_mark[i] = 0u;
   Ctrl *ctrl = a.ctrl;
-  if (tid == 0) {
+  if (tid0 == 0) {
     s_exit = ld_rlx(&ctrl->status) != 0;
     s_solve = -1;
+    s_idle = 0;
+    s_gmin = 0;
   }
   __syncthreads();
   if (s_exit) return;
 
   const unsigned long long t_start = wall_clock64();
-  const int start_word = (int)((blockIdx.x * 2654435761u) % (unsigned)a.nabw);
   int rounds = 0;
-  int stay = -1;
+  int stay = -1;  // unit kept from the previous batch (still holding work)
+  uint32_t mixkey = blockIdx.x * 0x85EBCA6Bu;
+  unsigned long long umv[4], um0[4];
 
   for (;;) {
-    // ---------------------------------------------------------- pick a unit
+    // thread-derived offsets are recomputed every batch rather than held live
+    const int tid = opaque_v(tid0);
+    const int lane = tid & (WAVE - 1);
+    const int wid = tid / WAVE;
+    // ------------------------------------------------------------- 1. pick
     if (tid == 0) {
       s_unit = -1;
       if (ld_rlx(&ctrl->done)) {
@@ -161,272 +218,487 @@ __global__ __launch_bounds__(BS) void k_solve(SolveArgs a) {
     }
     __syncthreads();
     if (s_exit) break;
-
-    int unit = stay;
-    if (unit < 0) {
-      for (int base = 0; base < a.nabw; base += BS) {
-        const int i = base + tid;
-        int found = 0x7FFFFFFF;
-        if (i < a.nabw) {
-          int wi = start_word + i;
-          if (wi >= a.nabw) wi -= a.nabw;
-          if (ld_rlx(&a.abits[wi])) found = i;
+    mixkey += 0x27D4EB2Fu;
+    uint32_t *const abits = opaque(a.abits);
+    unsigned long long *const unit_min = opaque(a.unit_min);
+    if (stay < 0) {
+      // global least pending minimum over the active units (an active unit
+      // whose minimum is not known yet counts as +inf and stays eligible)
+      unsigned long long gl = ~0ull;
+      uint32_t act0 = 0;
+      for (int u0 = 0; u0 < a.nunits; u0 += BS * 4) {
+        uint32_t wv[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int u = u0 + j * BS + tid;
+          wv[j] = u < a.nunits ? ld_rlx(&abits[u >> 5]) : 0u;
         }
-        found = wave_min(found);
-        if (lane_id() == 0) s_ws[tid / WAVE] = found;
-        __syncthreads();
-        if (tid == 0) {
-          int mn = 0x7FFFFFFF;
-          for (int k = 0; k < NW; k++) mn = s_ws[k] < mn ? s_ws[k] : mn;
-          if (mn != 0x7FFFFFFF) {
-            int wi = start_word + mn;
-            if (wi >= a.nabw) wi -= a.nabw;
-            uint32_t bits = ld_rlx(&a.abits[wi]);
-            const int r = blockIdx.x & 31;
-            while (bits) {
-              // rotate the pick by block id to spread workgroups over units
-              uint32_t rot = (bits >> r) | (bits << ((32 - r) & 31));
-              int b = (__ffs(rot) - 1 + r) & 31;
-              uint32_t mb = 1u << b;
-              uint32_t old = aand_acq(&a.abits[wi], ~mb);
-              if (old & mb) {
-                s_unit = wi * 32 + b;
-                break;
-              }
-              bits = old & ~mb;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int u = u0 + j * BS + tid;
+          umv[j] = ~0ull;
+          const bool act = u < a.nunits && ((wv[j] >> (u & 31)) & 1u);
+          if (act) umv[j] = ld_rlx(&unit_min[u]);
+          if (u0 == 0) {
+            um0[j] = umv[j];
+            act0 |= (uint32_t)act << j;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) gl = umv[j] < gl ? umv[j] : gl;
+      }
+      gl = wave_min(gl);
+      if (lane == 0) s_red[wid] = gl;
+      __syncthreads();
+      unsigned long long gmin = s_red[0];
+#pragma unroll
+      for (int k = 1; k < NW; k++) gmin = s_red[k] < gmin ? s_red[k] : gmin;
+      __syncthreads();
+      // random choice among the active units within the lag window of gmin
+      unsigned long long best = ~0ull;
+      for (int u0 = 0; u0 < a.nunits; u0 += BS * 4) {
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int u = u0 + j * BS + tid;
+          bool act;
+          unsigned long long d;
+          if (u0 == 0) {
+            act = (act0 >> j) & 1u;
+            d = um0[j];
+          } else {
+            act = u < a.nunits && ((ld_rlx(&abits[u >> 5]) >> (u & 31)) & 1u);
+            d = act ? ld_rlx(&unit_min[u]) : ~0ull;
+          }
+          if (act && (d == ~0ull || gmin == ~0ull || a.window == DELTA_INF ||
+                      Dist<WT>::within(d, gmin, a.window))) {
+            const unsigned long long key = unit_mix((uint32_t)u, mixkey);
+            best = key < best ? key : best;
+          }
+        }
+      }
+      best = wave_min(best);
+      if (lane == 0) s_red[wid] = best;
+      __syncthreads();
+      if (tid == 0) {
+        // try the per-wave picks in increasing key order (unrolled selection)
+        uint32_t tried = 0;
+        for (int it = 0; it < NW; it++) {
+          unsigned long long bk = ~0ull;
+          int bi = -1;
+#pragma unroll
+          for (int k = 0; k < NW; k++) {
+            const unsigned long long ck = s_red[k];
+            if (!((tried >> k) & 1u) && ck < bk) {
+              bk = ck;
+              bi = k;
             }
           }
-          s_ws[NW] = mn;
-        }
-        __syncthreads();
-        const int mn = s_ws[NW];
-        __syncthreads();
-        if (mn != 0x7FFFFFFF) break;
-      }
-      unit = s_unit;
-    }
-
-    if (unit < 0) {
-      // idle: finished when no work is pending anywhere
-      if (tid == 0) {
-        if (ld_rlx(&ctrl->work) <= 0) {
-          st_rlx(&ctrl->done, 1u);
-          s_exit = 1;
+          if (bi < 0) break;
+          tried |= 1u << bi;
+          const int u = (int)unit_unmix((uint32_t)bk, mixkey);
+          const uint32_t mb = 1u << (u & 31);
+          if (aand_acq(&abits[u >> 5], ~mb) & mb) {
+            s_unit = u;
+            s_gmin = gmin;
+            break;
+          }
         }
       }
       __syncthreads();
+    } else if (tid == 0) {
+      s_unit = stay;
+    }
+    if (stay < 0 && s_unit < 0 && tid == 0) s_idle = s_idle < 7 ? s_idle + 1 : 7;
+    if (s_unit >= 0 && tid == 0) s_idle = 0;
+    __syncthreads();
+    const int unit = uni(s_unit);
+    if (unit < 0) {
+      // idle: finished when no work is pending anywhere
+      if (tid == 0 && ld_rlx(&ctrl->work) <= 0) {
+        st_rlx(&ctrl->done, 1u);
+        s_exit = 1;
+      }
+      __syncthreads();
       if (s_exit) break;
-      __builtin_amdgcn_s_sleep(16);
+      for (int k = 0; k < (1 << s_idle); k++) __builtin_amdgcn_s_sleep(16);
       continue;
     }
 
-    // ------------------------------------------------- unit -> descriptor
     if (tid == 0) {
       const int sv = a.unit_solve[unit];
       if (sv != s_solve) {
         s_solve = sv;
         s_desc = a.desc[sv];
       }
+      // pushes from now on lower this with atomic min; the gather below
+      // covers every inbox bit set before this store
+      st_rlx(&unit_min[unit], LABEL_INF);
+      s_nlist = 0;
+      s_cnt = 0;
+      s_claimed = 0;
+      s_far = ~0ull;
+      s_lmin = ~0ull;
+      s_push = 0;
+      s_upd = 0;
+      s_cross = 0;
+      s_new = 0;
+      s_tot = 0;
+      s_exp = 0;
     }
     __syncthreads();
-    const int n = s_desc.n;
-    const int m = s_desc.m;
-    const int bsize = s_desc.bsize;
-    const int source = s_desc.source;
-    const int unit0 = s_desc.unit0;
-    const unsigned long long delta = s_desc.delta;
-    const int32_t *__restrict__ row_ptr = s_desc.row_ptr;
-    const int32_t *__restrict__ col = s_desc.col;
-    const uint32_t *__restrict__ wgt = s_desc.w;
-    unsigned long long *label = s_desc.label;
-    uint32_t *dirty = s_desc.dirty;
-
+    const int n = uni(s_desc.n);
+    const int m = uni(s_desc.m);
+    const int bsize = uni(s_desc.bsize);
+    const int source = uni(s_desc.source);
+    const int unit0 = uni(s_desc.unit0);
+    const unsigned long long delta = uni64(s_desc.delta);
+    const int32_t *__restrict__ row_ptr = uni_ptr(s_desc.row_ptr);
+    const int32_t *__restrict__ col = uni_ptr(s_desc.col);
+    const uint32_t *__restrict__ wgt = uni_ptr(s_desc.w);
+    unsigned long long *label = uni_ptr(s_desc.label);
+    uint32_t *dirty = uni_ptr(s_desc.dirty);
     const int part = unit - unit0;
     const int vlo = part * bsize;
     const int vhi = min(n, vlo + bsize);
     const int wlo = vlo >> 5;
     const int whi = (vhi - 1) >> 5;
 
-    // ------------------------------ gather + claim the lowest bucket (<= 2 tries)
-    unsigned long long T = ld_rlx(&a.thresh[unit]);
-    int cnt = 0;
-    for (int attempt = 0; attempt < 2; attempt++) {
-      if (tid == 0) {
-        s_cnt = 0;
-        s_left = 0;
-        s_min = ~0ull;
-        s_claimed = 0;
-      }
-      __syncthreads();
-      for (int wi = wlo + tid; wi <= whi; wi += BS) {
+    // ------------------------------------------------ 2. gather the inbox
+    for (int wb = wlo; wb <= whi; wb += BS) {
+      const int wi = wb + tid;
+      uint32_t bits = 0;
+      if (wi <= whi) {
         uint32_t mask = ~0u;
         if (wi == wlo) mask &= ~0u << (vlo & 31);
         if (wi == whi) {
           const int hb = (vhi - 1) & 31;
           mask &= hb == 31 ? ~0u : ((1u << (hb + 1)) - 1u);
         }
-        const uint32_t bits = ld_rlx(&dirty[wi]) & mask;
-        if (!bits) continue;
-        uint32_t near = 0;
-        unsigned long long mn = ~0ull;
-        for (uint32_t b = bits; b; b &= b - 1) {
-          const int k = __ffs(b) - 1;
-          const unsigned long long dv = ld_rlx(&label[wi * 32 + k]) >> 32;
-          if (dv < T) near |= 1u << k;
-          else mn = dv < mn ? dv : mn;
-        }
-        if (near) {
-          const int c = __popc(near);
-          const int base = atomicAdd(&s_cnt, c);
-          if (base >= FCAP) {
-            near = 0;
-          } else if (base + c > FCAP) {
-            uint32_t keep = 0, t = near;
-            for (int j = 0; j < FCAP - base; j++) {
-              keep |= t & (~t + 1u);
-              t &= t - 1;
-            }
-            near = keep;
-          }
-          if (near) {
-            const uint32_t got = aand_acq(&dirty[wi], ~near) & near;
-            int j = base;
-            for (uint32_t b = near; b; b &= b - 1) {
-              const int k = __ffs(b) - 1;
-              s_v[j++] = (got >> k) & 1u ? wi * 32 + k : -1;
-            }
-          }
-        }
-        if (bits & ~near) s_left = 1;
-        if (mn != ~0ull) atomicMin(&s_min, mn);
+        bits = ld_rlx(&dirty[wi]) & mask;
       }
+      int tot;
+      const int before = s_nlist;
+      int j = before + block_excl_scan<BS>(__popc(bits), s_ws, &tot);
+      for (uint32_t b = bits; b; b &= b - 1) {
+        if (j < FCAP) s_rs[j] = wi * 32 + __ffs(b) - 1;
+        j++;
+      }
+      if (tid == 0) s_nlist = before + tot;
       __syncthreads();
-      cnt = min(s_cnt, FCAP);
-      const unsigned long long smin = s_min;
-      if (cnt > 0 || smin == ~0ull) break;
-      // nothing in the current bucket but later ones are not empty: open the
-      // lowest non-empty bucket
-      T = Dist<WT>::bucket_end(smin, delta);
-      if (tid == 0) amax(&a.thresh[unit], T);
-      __syncthreads();
+      if (s_nlist >= FCAP) break;
     }
-    if (tid == 0 && s_left) aor(&a.abits[unit >> 5], 1u << (unit & 31));
-    if (cnt == 0) {
+    const int nlist = uni(min(s_nlist, FCAP));
+    const bool trunc = s_nlist > FCAP || (s_nlist == FCAP);
+    if (nlist == 0) {
+      // the unit's bits were taken by another workgroup meanwhile
       stay = -1;
       __syncthreads();
       continue;
     }
-
-    // ------------------------------------------ stage rows of the frontier
-    int degs[EPT];
-    int lsum = 0, nclaim = 0;
+    unsigned long long lmin = ~0ull;
+    for (int k0 = 0; k0 < nlist; k0 += BS * 4) {
+      unsigned long long lab[4];
 #pragma unroll
-    for (int j = 0; j < EPT; j++) {
-      const int k = tid * EPT + j;
-      int deg = 0;
-      if (k < cnt) {
-        const int u = s_v[k];
-        int rs = 0;
-        if (u >= 0) {
-          nclaim++;
-          const unsigned long long lab = ld_rlx(&label[u]);
-          s_d[k] = (uint32_t)(lab >> 32);
-          rs = row_ptr[u];
-          int re = row_ptr[u + 1];
-          if (rs < 0 || re < rs || re > m) {
-            set_status(&ctrl->status, SSSP_ERR_CSR);
-            rs = 0;
-            re = 0;
-          }
-          deg = re - rs;
+      for (int j = 0; j < 4; j++) {
+        const int k = k0 + j * BS + tid;
+        lab[j] = k < nlist ? ld_rlx(&label[s_rs[k]]) : ~0ull;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int k = k0 + j * BS + tid;
+        if (k < nlist) {
+          const uint32_t dv = (uint32_t)(lab[j] >> 32);
+          s_d[k] = dv;
+          lmin = dv < lmin ? dv : lmin;
         }
-        s_rs[k] = rs;
       }
-      degs[j] = deg;
-      lsum += deg;
     }
-    nclaim = wave_sum(nclaim);
-    if (lane_id() == 0 && nclaim) atomicAdd(&s_claimed, nclaim);
-    int tot;
-    int run = block_excl_scan<BS>(lsum, s_ws, &tot);
+    for (int i = tid; i <= whi - wlo; i += BS) s_off[i] = 0;
+    lmin = wave_min(lmin);
+    if (lane == 0) s_red[wid] = lmin;
+    __syncthreads();
+    unsigned long long umin = s_red[0];
 #pragma unroll
-    for (int j = 0; j < EPT; j++) {
-      const int k = tid * EPT + j;
-      if (k < cnt) s_off[k] = run;
-      run += degs[j];
+    for (int k = 1; k < NW; k++) umin = s_red[k] < umin ? s_red[k] : umin;
+    const unsigned long long T = Dist<WT>::bucket_end(umin, delta);
+    // near masks per inbox word; far minimum
+    unsigned long long far = ~0ull;
+    for (int k = tid; k < nlist; k += BS) {
+      const uint32_t dv = s_d[k];
+      const int v = s_rs[k];
+      if ((unsigned long long)dv < T) atomicOr((unsigned int *)&s_off[(v >> 5) - wlo], 1u << (v & 31));
+      else far = dv < far ? dv : far;
     }
-    if (tid == 0) {
-      s_off[cnt] = tot;
-      // raise the pending count by an upper bound of the inbox bits this
-      // batch can set, before any of them is published
-      if (tot) aadd(&ctrl->work, (long long)tot);
-      s_upd = 0;
-      s_cross = 0;
-      s_new = 0;
-      s_push = 0;
+    far = wave_min(far);
+    if (lane == 0 && far != ~0ull) atomicMin(&s_far, far);
+    __syncthreads();
+    // one atomic and-not per word (done by the first listed vertex of the
+    // word), then every listed near vertex checks whether it was claimed
+    for (int k = tid; k < nlist; k += BS) {
+      const int v = s_rs[k];
+      const int w = v >> 5;
+      if (k == 0 || (s_rs[k - 1] >> 5) != w) {
+        const uint32_t mk = (uint32_t)s_off[w - wlo];
+        if (mk) s_off[w - wlo] = (int32_t)(aand_acq(&dirty[w], ~mk) & mk);
+      }
     }
     __syncthreads();
+    for (int k = tid; k < nlist; k += BS) {
+      const int v = s_rs[k];
+      if (((uint32_t)s_off[(v >> 5) - wlo] >> (v & 31)) & 1u) {
+        if ((unsigned long long)s_d[k] < T) s_v[atomicAdd(&s_cnt, 1)] = v;
+      }
+    }
+    __syncthreads();
+    const int cnt = uni(s_cnt);
 
-    // ---------------------------------------------- edge-parallel relaxation
-    unsigned int upd = 0, cross = 0, nnew = 0;
-    int push = 0;
-    for (int idx = tid; idx < tot; idx += BS) {
-      int lo = 0, hi = cnt - 1;  // last k with s_off[k] <= idx
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_off[mid] <= idx) lo = mid;
-        else hi = mid - 1;
+    // ---------------------------------------- 3-4. settle the bucket locally
+    // Rounds: stage the frontier's rows, relax every arc; heads in this
+    // partition that land in the current bucket form the next round's
+    // frontier in LDS (deduplicated by an LDS bitmap) instead of going
+    // through the inbox, so the partition settles its bucket in one batch.
+    // Each round first raises the pending count by m + FCAP, an upper bound
+    // of the inbox bits it can set (thread 0's round trip overlaps the
+    // staging loads); the batch returns the surplus once at the end.
+    int cur_cnt = cnt;
+    int nround = 0;
+    long long raised = 0;  // thread 0 only
+    for (;;) {
+      if (tid == 0) {
+        // the returned value is consumed so that the add has completed before
+        // thread 0 reaches the barrier below (no inbox bit of this round is
+        // published before that barrier)
+        const long long before = aadd(&ctrl->work, (long long)m + FCAP);
+        raised += (long long)m + FCAP;
+        s_ncnt = before == LLONG_MIN ? 1 : 0;
       }
-      const int e = s_rs[lo] + (idx - s_off[lo]);
-      const int v = col[e];
-      const uint32_t wv = wgt[e];
-      if ((unsigned)v >= (unsigned)n) {
-        set_status(&ctrl->status, SSSP_ERR_CSR);
-        continue;
+      for (int k0 = 0; k0 < cur_cnt; k0 += BS * 4) {
+        unsigned long long lab[4];
+        int rs[4], re[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int k = k0 + j * BS + tid;
+          if (k < cur_cnt) {
+            const int u = s_v[k];
+            lab[j] = ld_rlx(&label[u]);
+            rs[j] = row_ptr[u];
+            re[j] = row_ptr[u + 1];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int k = k0 + j * BS + tid;
+          if (k < cur_cnt) {
+            int r0 = rs[j], r1 = re[j];
+            if (r0 < 0 || r1 < r0 || r1 > m) {
+              set_status(&ctrl->status, SSSP_ERR_CSR);
+              r0 = 0;
+              r1 = 0;
+            }
+            s_d[k] = (uint32_t)(lab[j] >> 32);
+            s_rs[k] = r0;
+            s_off[k] = r1 - r0;
+          }
+        }
       }
-      if (v == source) continue;
-      bool ovf;
-      const uint32_t nd = Dist<WT>::add(s_d[lo], wv, ovf);
-      if (ovf) {
-        set_status(&ctrl->status, SSSP_ERR_OVERFLOW);
-        continue;
+      __syncthreads();
+      int degs[EPT];
+      int lsum = 0;
+#pragma unroll
+      for (int j = 0; j < EPT; j++) {
+        const int k = tid * EPT + j;
+        degs[j] = k < cur_cnt ? s_off[k] : 0;
+        lsum += degs[j];
       }
-      const unsigned long long packed = ((unsigned long long)nd << 32) | (uint32_t)e;
-      if (packed >= ld_rlx(&label[v])) continue;
-      const unsigned long long old = amin(&label[v], packed);
-      if ((uint32_t)(old >> 32) <= nd) continue;  // distance not lowered
-      upd++;
-      const int q = v / bsize;
-      if (q != part) cross++;
-      const uint32_t bit = 1u << (v & 31);
-      if (aor(&dirty[v >> 5], bit) & bit) continue;  // already pending
-      nnew++;
-      if (q != part) {
-        const int gu = unit0 + q;
-        const uint32_t ab = 1u << (gu & 31);
-        if (!(ld_rlx(&a.abits[gu >> 5]) & ab)) aor(&a.abits[gu >> 5], ab);
-      } else {
-        push = 1;
+      int tot;
+      int run = block_excl_scan<BS>(lsum, s_ws, &tot);
+#pragma unroll
+      for (int j = 0; j < EPT; j++) {
+        const int k = tid * EPT + j;
+        if (k < cur_cnt) s_off[k] = run;
+        run += degs[j];
       }
+      if (tid == 0) s_off[cur_cnt] = tot;
+      __syncthreads();
+
+      unsigned int upd = 0, cross = 0, nnew = 0;
+      unsigned long long pmin = ~0ull;
+      int hint = 0;
+      for (int b0 = 0; b0 < tot; b0 += BS * U) {
+        int e[U], v[U];
+        uint32_t du[U], wv[U], nd[U];
+        bool act[U];
+#pragma unroll
+        for (int j = 0; j < U; j++) {
+          const int idx = b0 + j * BS + tid;
+          act[j] = idx < tot;
+          if (act[j]) {
+            // last k with s_off[k] <= idx, galloping up from the previous k
+            int lo = hint, step = 1;
+            while (lo + step < cur_cnt && s_off[lo + step] <= idx) {
+              lo += step;
+              step <<= 1;
+            }
+            int hi = min(lo + step, cur_cnt) - 1;
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (s_off[mid] <= idx) lo = mid;
+              else hi = mid - 1;
+            }
+            hint = lo;
+            e[j] = s_rs[lo] + (idx - s_off[lo]);
+            du[j] = s_d[lo];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < U; j++)
+          if (act[j]) {
+            v[j] = col[e[j]];
+            wv[j] = wgt[e[j]];
+          }
+        unsigned long long pk[U], cur[U];
+#pragma unroll
+        for (int j = 0; j < U; j++) {
+          if (!act[j]) continue;
+          if ((unsigned)v[j] >= (unsigned)n) {
+            set_status(&ctrl->status, SSSP_ERR_CSR);
+            act[j] = false;
+            continue;
+          }
+          bool ovf;
+          nd[j] = Dist<WT>::add(du[j], wv[j], ovf);
+          if (ovf) {
+            set_status(&ctrl->status, SSSP_ERR_OVERFLOW);
+            act[j] = false;
+            continue;
+          }
+          if (v[j] == source) {
+            act[j] = false;
+            continue;
+          }
+          pk[j] = ((unsigned long long)nd[j] << 32) | (uint32_t)e[j];
+          cur[j] = ld_rlx(&label[v[j]]);
+        }
+#pragma unroll
+        for (int j = 0; j < U; j++) {
+          if (act[j] && pk[j] < cur[j]) cur[j] = amin(&label[v[j]], pk[j]);
+          else act[j] = false;
+        }
+        // lowered distances: same partition and same bucket -> next round in
+        // LDS; otherwise -> the owner's inbox bit
+        bool inbox[U];
+#pragma unroll
+        for (int j = 0; j < U; j++) {
+          inbox[j] = false;
+          if (!act[j] || (uint32_t)(cur[j] >> 32) <= nd[j]) {
+            act[j] = false;
+            continue;
+          }
+          upd++;
+          const int q = v[j] / bsize;
+          if (q != part) {
+            cross++;
+            inbox[j] = true;
+          } else if ((unsigned long long)nd[j] < T) {
+            const int lv = v[j] - vlo;
+            const uint32_t mb = 1u << (lv & 31);
+            if (!(atomicOr(&s_mark[lv >> 5], mb) & mb)) {
+              const int slot = atomicAdd(&s_ncnt, 1);
+              if (slot < FCAP) s_nv[slot] = v[j];
+              else {
+                atomicAnd(&s_mark[lv >> 5], ~mb);
+                inbox[j] = true;
+              }
+            }
+          } else {
+            inbox[j] = true;
+          }
+        }
+        uint32_t ob[U];
+#pragma unroll
+        for (int j = 0; j < U; j++)
+          if (inbox[j]) ob[j] = aor(&dirty[v[j] >> 5], 1u << (v[j] & 31));
+#pragma unroll
+        for (int j = 0; j < U; j++) {
+          if (!inbox[j] || ((ob[j] >> (v[j] & 31)) & 1u)) continue;  // already pending
+          nnew++;
+          const int q = v[j] / bsize;
+          if (q != part) {
+            const int gu = unit0 + q;
+            amin(&unit_min[gu], (unsigned long long)nd[j]);
+            aor(&abits[gu >> 5], 1u << (gu & 31));
+          } else {
+            pmin = nd[j] < pmin ? nd[j] : pmin;
+          }
+        }
+      }
+      upd = wave_sum(upd);
+      cross = wave_sum(cross);
+      nnew = wave_sum(nnew);
+      pmin = wave_min(pmin);
+      if (lane == 0) {
+        if (upd) atomicAdd(&s_upd, upd);
+        if (cross) atomicAdd(&s_cross, cross);
+        if (nnew) atomicAdd(&s_new, nnew);
+        if (pmin != ~0ull) atomicMin(&s_lmin, pmin);
+      }
+      if (tid == 0) {
+        s_tot += tot;
+        s_exp += cur_cnt;
+      }
+      __syncthreads();
+      const int ncnt = uni(min(s_ncnt, FCAP));
+      nround++;
+      if (ncnt == 0) break;
+      if (nround >= MAX_ROUNDS_PER_BATCH) {
+        // hand the queued vertices back to the inbox (covered by this
+        // round's raise) and stop
+        unsigned int fl = 0;
+        for (int k = tid; k < ncnt; k += BS) {
+          const int v2 = s_nv[k];
+          const int lv = v2 - vlo;
+          atomicAnd(&s_mark[lv >> 5], ~(1u << (lv & 31)));
+          const uint32_t bit = 1u << (v2 & 31);
+          if (!(aor(&dirty[v2 >> 5], bit) & bit)) fl++;
+        }
+        fl = wave_sum(fl);
+        if (lane == 0 && fl) atomicAdd(&s_new, fl);
+        if (tid == 0) atomicMin(&s_lmin, umin);
+        __syncthreads();
+        break;
+      }
+      for (int k = tid; k < ncnt; k += BS) {
+        const int v2 = s_nv[k];
+        const int lv = v2 - vlo;
+        atomicAnd(&s_mark[lv >> 5], ~(1u << (lv & 31)));
+        s_v[k] = v2;
+      }
+      cur_cnt = ncnt;
+      __syncthreads();
     }
-    upd = wave_sum(upd);
-    cross = wave_sum(cross);
-    nnew = wave_sum(nnew);
-    if (lane_id() == 0) {
-      if (upd) atomicAdd(&s_upd, upd);
-      if (cross) atomicAdd(&s_cross, cross);
-      if (nnew) atomicAdd(&s_new, nnew);
-    }
-    if (push) s_push = 1;
-    __syncthreads();
+
+    // ------------------------------------------------------ 5. settle
     if (tid == 0) {
-      // every consequence of this batch is published: settle the count
-      aadd(&ctrl->work, (long long)s_new - (long long)tot - (long long)s_claimed);
+      // every consequence of this batch is published: return the surplus
+      aadd(&ctrl->work, (long long)s_new - raised - (long long)cnt);
+      unsigned long long rem = s_far < s_lmin ? s_far : s_lmin;
+      if (trunc) rem = umin < rem ? umin : rem;
+      s_stay = -1;
+      if (rem != ~0ull) {
+        amin(&unit_min[unit], rem);
+        // keep the unit while its remaining work is within the lag window of
+        // the least pending distance seen at the pick; otherwise (or when it
+        // overflowed the frontier) let any workgroup take it
+        if (!trunc && (a.window == DELTA_INF || Dist<WT>::within(rem, s_gmin, a.window)))
+          s_stay = unit;
+        else
+          aor(&abits[unit >> 5], 1u << (unit & 31));
+      }
       if (a.stats) {
-        stat_add(&a.stats->edges_relaxed, (uint64_t)tot);
+        stat_add(&a.stats->edges_relaxed, (uint64_t)s_tot);
         stat_add(&a.stats->label_updates, (uint64_t)s_upd);
         stat_add(&a.stats->cross_updates, (uint64_t)s_cross);
-        stat_add(&a.stats->vertices_expanded, (uint64_t)s_claimed);
+        stat_add(&a.stats->vertices_expanded, (uint64_t)s_exp);
         stat_add(&a.stats->batches, 1);
       }
       if (a.max_rounds > 0 && ++rounds >= a.max_rounds) {
@@ -434,8 +706,8 @@ __global__ __launch_bounds__(BS) void k_solve(SolveArgs a) {
         st_rlx(&ctrl->done, 1u);
       }
     }
-    stay = s_push ? unit : -1;
     __syncthreads();
+    stay = s_stay;
   }
 }
 
@@ -483,7 +755,8 @@ __global__ void k_epilogue(SolveArgs a) {
 }
 
 // ------------------------------------------------------------- validation
-// CSR and weight checks; the first violation is written to *status.
+// CSR and weight checks; the first violation is written to *status.  Rows
+// are checked for sortedness one wave per row (rows can be very long).
 __global__ void k_validate(const int32_t *row_ptr, const int32_t *col, const uint32_t *w,
                            int n, int m, int wtype, int need_sorted, int need_positive,
                            int32_t *status) {
@@ -492,16 +765,18 @@ __global__ void k_validate(const int32_t *row_ptr, const int32_t *col, const uin
   if (t == 0 && (row_ptr[0] != 0 || row_ptr[n] != m)) set_status(status, SSSP_ERR_CSR);
   for (int u = t; u < n; u += stride) {
     const int a = row_ptr[u], b = row_ptr[u + 1];
-    if (a > b || a < 0 || b > m) {
-      set_status(status, SSSP_ERR_CSR);
-      continue;
+    if (a > b || a < 0 || b > m) set_status(status, SSSP_ERR_CSR);
+  }
+  if (need_sorted) {
+    const int wave = t / WAVE;
+    const int nwaves = stride / WAVE;
+    for (int u = wave; u < n; u += nwaves) {
+      const int a = row_ptr[u], b = row_ptr[u + 1];
+      if (a > b || a < 0 || b > m) continue;
+      bool bad = false;
+      for (int e = a + 1 + lane_id(); e < b; e += WAVE) bad |= col[e] < col[e - 1];
+      if (__ballot(bad) && lane_id() == 0) set_status(status, SSSP_ERR_UNSORTED);
     }
-    if (need_sorted)
-      for (int e = a + 1; e < b; e++)
-        if (col[e] < col[e - 1]) {
-          set_status(status, SSSP_ERR_UNSORTED);
-          break;
-        }
   }
   for (int e = t; e < m; e += stride) {
     if ((unsigned)col[e] >= (unsigned)n) set_status(status, SSSP_ERR_CSR);

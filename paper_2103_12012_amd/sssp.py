@@ -18,7 +18,7 @@ from dataclasses import dataclass
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsssp.so")
+LIB_PATH = os.environ.get("SSSP_LIB", os.path.join(_HERE, "libsssp.so"))
 HEADER = os.path.join(_HERE, "..", "include", "sssp.h")
 
 W_U32, W_F32 = 0, 1
@@ -49,7 +49,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_double), ("num_partitions", ctypes.c_int32),
                 ("wg_size", ctypes.c_int32), ("num_workgroups", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_int32), ("event_start", ctypes.c_void_p),
+                ("lag", ctypes.c_int32), ("event_start", ctypes.c_void_p),
                 ("event_stop", ctypes.c_void_p)]
 
 
@@ -145,7 +145,8 @@ def _csr(row_ptr, col, w) -> CSR:
 
 
 def make_opts(delta=0.0, num_partitions=0, wg_size=0, num_workgroups=0, max_rounds=0,
-              validate=True, sync=False, local=False, no_autotune=False, events=None) -> Opts:
+              validate=True, sync=False, local=False, no_autotune=False, events=None,
+              lag=0) -> Opts:
     flags = (F_VALIDATE if validate else 0) | (F_SYNC if sync else 0) | \
             (F_PRUNE_LOCAL if local else 0) | (F_NO_AUTOTUNE if no_autotune else 0)
     o = Opts()
@@ -155,7 +156,7 @@ def make_opts(delta=0.0, num_partitions=0, wg_size=0, num_workgroups=0, max_roun
     o.num_workgroups = int(num_workgroups)
     o.max_rounds = int(max_rounds)
     o.flags = flags
-    o.reserved = 0
+    o.lag = int(lag)
     if events is not None:
         o.event_start, o.event_stop = events
     return o
@@ -228,11 +229,11 @@ class Solver:
 
     def __init__(self, row_ptr, col, w, *, delta=0.0, num_partitions=0, wg_size=0,
                  num_workgroups=0, max_rounds=0, validate=True, want_pred=True,
-                 stats=False):
+                 stats=False, lag=0):
         self.g = _csr(row_ptr, col, w)
         self._keep = (row_ptr, col, w)
         self.opts = make_opts(delta, num_partitions, wg_size, num_workgroups, max_rounds,
-                              validate=validate)
+                              validate=validate, lag=lag)
         dev = col.device
         n = self.g.n
         self.dist = torch.empty(n, dtype=w.dtype, device=dev)
@@ -376,13 +377,14 @@ class SSSPDist(torch.autograd.Function):
 
 
 # ------------------------------------------------------------------ autotune
-def autotune(row_ptr, col, w, source: int, cache_path: str | None = None) -> dict:
+def autotune(row_ptr, col, w, source: int, cache_path: str | None = None, **fixed) -> dict:
     """Time candidate settings for this graph; the winner is cached in the
-    library and returned as a dict of options."""
+    library and returned as a dict of options.  Keyword arguments (delta,
+    num_partitions, wg_size, num_workgroups, lag) fix those options."""
     g = _csr(row_ptr, col, w)
     L = lib()
     dev = col.device
-    best = Opts()
+    best = make_opts(validate=False, **fixed)
     ws = _workspace(lambda nb: L.sssp_autotune(ctypes.byref(g), int(source), None,
                                                ctypes.byref(best), None, None, nb, None), dev)
     scratch = torch.empty(g.n, dtype=torch.int32, device=dev)
@@ -392,7 +394,7 @@ def autotune(row_ptr, col, w, source: int, cache_path: str | None = None) -> dic
                          _ptr(ws), ctypes.byref(nb), _stream())
     _check(rc, "sssp_autotune")
     return {"delta": best.delta, "num_partitions": best.num_partitions,
-            "wg_size": best.wg_size, "num_workgroups": best.num_workgroups}
+            "wg_size": best.wg_size, "num_workgroups": best.num_workgroups, "lag": best.lag}
 
 
 # ------------------------------------------------------------------ helpers

@@ -70,9 +70,8 @@ def test_solve_host_errors(lib):
     assert ws_query(lib, fake_csr(), source=10)[0] == -2
     assert ws_query(lib, fake_csr(), opts=sssp.make_opts(wg_size=100))[0] == -1
     assert ws_query(lib, fake_csr(), opts=sssp.make_opts(delta=float("nan")))[0] == -1
-    o = sssp.make_opts()
-    o.reserved = 3
-    assert ws_query(lib, fake_csr(), opts=o)[0] == -1
+    assert ws_query(lib, fake_csr(), opts=sssp.make_opts(num_partitions=-2))[0] == -1
+    assert ws_query(lib, fake_csr(), opts=sssp.make_opts(max_rounds=-1))[0] == -1
     assert lib.sssp_solve(None, 0, None, None, None, None, None, None, None, None) == -1
     g = fake_csr()
     assert lib.sssp_solve(ctypes.byref(g), 0, None, None, None, None, None, None, None,

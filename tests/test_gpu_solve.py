@@ -149,12 +149,13 @@ def test_rmat20_full_size_prune_then_solve():
     assert oracle.certify(g.row_ptr, g.col, g.w, s, dist, pe_orig) == (0, -1)
 
 
-@pytest.mark.skip(reason="the 4096x4096 grid solve currently exceeds the 10 s device time limit")
-def test_grid4096_full_size():
-    """Road-like grid at full size (16.8M vertices, 67M arcs) from a corner:
-    checked with the LP-dual certificate (exact distances and the
-    smallest-tight-edge predecessor) and against the oracle."""
+@pytest.mark.parametrize("opts", [dict(num_partitions=512, delta=4000, lag=2), dict()])
+def test_grid4096_full_size(opts):
+    """Road-like grid at full size (16.8M vertices, 67M arcs) from a corner,
+    with the tuned and with the default options: checked with the LP-dual
+    certificate (exact distances and the smallest-tight-edge predecessor)
+    and against the oracle."""
     g = gen.grid(4096, 4096, seed=3)
-    dist, pred, pe = gpu_solve(g, 0)
+    dist, pred, pe = gpu_solve(g, 0, **opts)
     assert oracle.certify(g.row_ptr, g.col, g.w, 0, dist, pe) == (0, -1)
     assert_solve_parity(g, 0, (dist, pred, pe))
