@@ -66,8 +66,50 @@ def m_reached(g, source):
     return int(g.out_degree()[mask].sum()), int(mask.sum())
 
 
-def roofline(name, bytes_alg, ms, bound="hbm", traffic=None):
+KERNEL_SOURCES = {  # files each kernel is compiled from (for the counter-staleness check)
+    "k_tb_main": ("internal.hpp", "prune.hip"),
+    "k_solve": ("internal.hpp", "solve.hip"),
+}
+
+
+def kernel_source_hash(kernel):
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2103_12012_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary profiles/pmc_<kernel>_<workload>.txt: FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch, one --pmc run each), each scaled by the factor the same
+    counter gives for a plain device copy of known size.  None when there is
+    no summary or the kernel's sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith((" ", "#", "-")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        if kv.get("source_sha256") != kernel_source_hash(kernel):
+            return None
+        fetch = float(kv["fetch_kib_per_dispatch"]) * 1024 * float(kv["copy_fetch_factor"])
+        write = float(kv["write_kib_per_dispatch"]) * 1024 * float(kv["copy_write_factor"])
+    except (KeyError, ValueError):
+        return None
+    return int(fetch + write)
+
+
+def roofline(name, bytes_alg, ms, bound="hbm", workload=None):
     gbs = bytes_alg / (ms * 1e-3) / 1e9
+    traffic = counter_traffic(name, workload) if workload else None
     return {"bound": bound, "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": name,
             "avg_launch_ms": round(ms, 4), "algorithmic_bytes": int(bytes_alg)}
@@ -133,16 +175,26 @@ def bench_rmat20(steps, warmup, cpu_leg=True):
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     ms_step = t_total / steps * 1e3
-    # per-kernel device times with HIP events on the launch stream
-    pr, so = [], []
-    for _ in range(max(3, min(steps, 10))):
+    # per-kernel device times: HIP events recorded by the library around its
+    # main kernel on the launch stream; whole-step times with stream events.
+    # The last-level cache (MALL) is flushed before each trial.
+    flush = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    pr, so, whole = [], [], []
+    for _ in range(max(10, steps)):
+        flush.fill_(1)
         e1 = ev.pair()
-        prune_step(e1)
         e2 = ev.pair()
+        t0e = torch.cuda.Event(enable_timing=True)
+        t1e = torch.cuda.Event(enable_timing=True)
+        t0e.record()
+        prune_step(e1)
         solver(s, events=e2)
+        t1e.record()
         torch.cuda.synchronize()
         pr.append(ev.ms(e1))
         so.append(ev.ms(e2))
+        whole.append(t0e.elapsed_time(t1e))
+    del flush
     st = solver.stats.read()
     dist = solver.dist.cpu().numpy().view(np.uint32)
     reached = int((dist != 0xFFFFFFFF).sum())
@@ -160,10 +212,15 @@ def bench_rmat20(steps, warmup, cpu_leg=True):
         "ms_per_step": ms_step,
         "solve_only_gteps": mcc / (solve_ms * 1e-3) / 1e9,
         "prune_ms": prune_ms, "solve_ms": solve_ms,
+        "trials": {"n": len(pr), "prune_main_ms_mean": prune_ms,
+                   "prune_main_ms_median": float(np.median(pr)),
+                   "solve_kernel_ms_mean": solve_ms, "solve_kernel_ms_median": float(np.median(so)),
+                   "step_ms_mean": float(np.mean(whole)), "step_ms_median": float(np.median(whole)),
+                   "mall_flushed": True},
         "n": g.n, "m": g.m, "m_kept": kept_m, "m_cc": mcc, "reached": reached, "source": s,
         "stats": st,
-        "roofline_solve": roofline("k_solve", b_solve, solve_ms),
-        "roofline_prune": roofline("k_tri_main", b_prune, prune_ms),
+        "roofline_solve": roofline("k_solve", b_solve, solve_ms, workload="rmat20"),
+        "roofline_prune": roofline("k_tb_main", b_prune, prune_ms, workload="rmat20"),
         "wedges": st.get("wedges"),
     }
     if cpu_leg:
@@ -176,7 +233,7 @@ def cpu_baseline_rmat20(g, s, mcc):
     all threads) on the whole graph, then binary-heap Dijkstra (one thread)."""
     import oracle
 
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = oracle.max_threads()
     t0 = time.perf_counter()
     keep = oracle.trishla(g.row_ptr, g.col, g.w)
     t1 = time.perf_counter()
@@ -189,9 +246,22 @@ def cpu_baseline_rmat20(g, s, mcc):
     t3 = time.perf_counter()
     step = (t1 - t0) + (t3 - t2)
     return {"value": round(mcc / step / 1e9, 5), "unit": "GTEPS", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "host": host_cpu(),
             "sample": f"one full step on the same R-MAT 20 graph: Trishla mark-array on "
                       f"{threads} threads {t1-t0:.2f}s + Dijkstra 1 thread {t3-t2:.2f}s"}
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0))}
 
 
 # ------------------------------------------------------------------ extras
@@ -236,6 +306,13 @@ def bench_batch(steps):
     mcc = 0
     for gi, s in zip(sg, ss):
         mcc += m_reached(graphs[gi], s)[0]
+    # autotune once per scale (the cache key is the graph signature); both the
+    # batched launch and the single calls below use the tuned options
+    tuned = {}
+    for gi, s in zip(sg, ss):
+        sc = int(scales[gi])
+        if sc not in tuned:
+            tuned[sc] = sssp.autotune(*dg[gi], s)
     b = sssp.BatchSolver(dg, sg, ss)
     b()
     torch.cuda.synchronize()
@@ -266,6 +343,7 @@ def bench_batch(steps):
     torch.cuda.synchronize()
     single_ms = (time.perf_counter() - t0) / steps * 1e3
     return {"workload": "batched_64rmat_12to18_x4", "solves": len(sg), "m_cc_total": mcc,
+            "tuned": {str(k): v for k, v in sorted(tuned.items())},
             "batch_ms": batch_ms, "batch_gteps": mcc / (batch_ms * 1e-3) / 1e9,
             "single_calls_ms": single_ms, "single_gteps": mcc / (single_ms * 1e-3) / 1e9}
 
@@ -312,6 +390,25 @@ def bench_diff(steps):
             "tolerance": "1e-5 rel dist (bit-exact expected), 1e-4 grad"}
 
 
+def bench_copy(steps):
+    """A plain device copy of 1 GiB: the calibration that scales the
+    FETCH_SIZE / WRITE_SIZE counters to bytes (each reads 1 GiB ideally)."""
+    import torch
+
+    n = 1 << 30
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    return {"workload": "device_copy_1GiB", "bytes_read": n, "bytes_written": n,
+            "ms": ms, "gbs": 2 * n / (ms * 1e-3) / 1e9}
+
+
 # ------------------------------------------------------------------ main
 def main():
     ap = argparse.ArgumentParser()
@@ -319,12 +416,13 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--only", nargs="*", default=None,
-                    help="subset of: rmat20 grid batch diff")
+                    help="subset of: rmat20 grid batch diff copy (copy: counter calibration, "
+                         "not part of the default run)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU (--gpus 1); multi-GPU sharding "
-              "is a design note only", file=sys.stderr)
+        print("bench.py runs on one GPU only (--gpus 1): the library has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -337,7 +435,8 @@ def main():
         head = bench_rmat20(args.steps, args.warmup, cpu_leg=not args.no_cpu)
         print(f"[bench] rmat20 done: {head['ms_per_step']:.3f} ms/step", file=sys.stderr,
               flush=True)
-    for name, fn in (("grid", bench_grid), ("batch", bench_batch), ("diff", bench_diff)):
+    for name, fn in (("grid", bench_grid), ("batch", bench_batch), ("diff", bench_diff),
+                     ("copy", bench_copy)):
         if name in only:
             extra[name] = fn(max(1, min(args.steps, 5)))
             print(f"[bench] {name} done", file=sys.stderr, flush=True)

@@ -220,7 +220,7 @@ int sssp_backward(const sssp_csr *g, int32_t source, const float *dist,
  * are kept fixed, the others are searched (delta over multiples of the mean
  * arc cost sampled from the device, and one unbounded bucket).  Results
  * are cached in the process, keyed by the device and a signature of the
- * graph (weight type, ceil(log2 n), rounded log2 of the average degree), and
+ * graph (weight type, ceil(log2 n), floor(log2) of the average degree), and
  * sssp_solve / sssp_solve_batch with automatic options consult the cache.
  * If cache_path is non-NULL the cache is loaded from and saved to that JSON
  * file.

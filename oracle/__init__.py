@@ -63,6 +63,11 @@ def _load():
     return _lib
 
 
+def max_threads() -> int:
+    """Threads the OpenMP routines (Trishla) run on."""
+    return int(_load().oracle_max_threads())
+
+
 def _p(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 

@@ -35,6 +35,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#include <omp.h>
 
 #define U64_INF UINT64_MAX
 
@@ -545,4 +546,15 @@ int oracle_grad_f32(int32_t n, const int32_t *row_ptr, int32_t source,
   for (int64_t e = 0; e < m; e++) grad_w[e] = (float)acc[e];
   free(acc);
   return rc;
+}
+
+/* Number of OpenMP threads the parallel oracle routines use. */
+int oracle_max_threads(void) {
+  int t = 1;
+#pragma omp parallel
+  {
+#pragma omp single
+    t = omp_get_num_threads();
+  }
+  return t;
 }

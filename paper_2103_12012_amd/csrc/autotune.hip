@@ -40,14 +40,14 @@ std::string device_tag() {
 }
 
 // Coarse signature: graphs of the same weight type, the same ceil(log2 n)
-// and a similar average degree share an entry.
+// and the same floor(log2) of the average degree share an entry.
 std::string graph_key(const sssp_csr &g) {
   int ln = 0;
   while ((1ll << ln) < (long long)g.n) ln++;
   const double avg = g.m > 0 ? (double)g.m / g.n : 0.0;
-  const int ld = avg > 0 ? (int)std::lround(4.0 * std::log2(avg)) : -99;
+  const int ld = avg > 0 ? (int)std::floor(std::log2(avg)) : -99;
   return device_tag() + "|w=" + std::to_string(g.wtype) + "|log2n=" + std::to_string(ln) +
-         "|4log2deg=" + std::to_string(ld);
+         "|log2deg=" + std::to_string(ld);
 }
 
 void load_json(const char *path) {

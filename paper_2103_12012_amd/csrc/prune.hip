@@ -6,9 +6,19 @@
 //
 // Edge-centric form: for every arc the shorter of the two lists is scanned
 // and every entry probed in a hash table of the longer one (keyed by the
-// middle vertex, holding the cheapest parallel arc).  The work is
+// middle vertex, holding the cheapest parallel arc).  The work is at most
 // sum_e min(|N_out(u)|, |N_in(x)|) probes instead of the
-// sum_y indeg(y) * outdeg(y) wedges of the literal per-vertex loop.
+// sum_y indeg(y) * outdeg(y) wedges of the literal per-vertex loop, and
+// far less in practice:
+//
+//  * every list of SORT_MIN+1 .. SORT_MAX entries is sorted by cost, so the
+//    scan of an arc of cost W stops at the first entry with cost >= W (no
+//    later entry can be the cheap half of a detour), and
+//  * the scan of an arc stops at its first witness.
+//
+// The scans advance in rounds: each live arc takes a chunk of its list
+// (16 entries, doubling every round), the chunks of all live arcs of a
+// batch are laid end to end over the lanes, and finished arcs drop out.
 //
 //  * arcs with |N_out(u)| <= |N_in(x)| ("x-side") are grouped by x and use
 //    the table of N_in(x); the others ("u-side") are grouped by u and use
@@ -33,10 +43,23 @@ constexpr int TB_NW = TB_BS / WAVE;
 constexpr int LT_DEG = 128;          // light owner: list length
 constexpr int LT_SLOTS = 256;        // light owner: wave-private hash slots
 constexpr int LT_WORK = 8192;        // light owner: probes
-constexpr int HV_TCAP = 8192;        // heavy owner: longest list in an LDS table
+constexpr int LT_BS = 256;
+constexpr int LT_CHUNK = 16;         // light owners dealt to a wave at a time
+constexpr int HM_TCAP = 2048;        // medium heavy owner: longest list
+constexpr int HM_SLOTS = 4096;
+constexpr int HM_BS = 256;
+constexpr int HM_Q = 256;            // medium: arcs staged per batch
+constexpr int HV_TCAP = 8192;        // big heavy owner: longest list in an LDS table
 constexpr int HV_SLOTS = 16384;
-constexpr int HV_Q = 1024;           // heavy: queries staged per round
-constexpr int HV_TARGET = 1 << 16;   // heavy: probes per item
+constexpr int HV_Q = 512;            // big: arcs staged per batch
+constexpr int ITEM_MINQ = 32;        // an item covers at least this many arcs
+constexpr int HV_TARGET = 1 << 18;   // heavy: estimated probes per item
+constexpr int SORT_MIN = 16;         // lists of SORT_MIN+1 .. SORT_MAX entries
+constexpr int SORT_MAX = 4096;       //   are sorted by cost
+constexpr int SORT_BS = 256;
+constexpr int SORT_WAVE = 4 * 64;    // longest list sorted by one wave
+constexpr int Q_D0 = 16;             // first scan chunk of an arc
+constexpr int Q_DMAX = 1024;         // chunk cap
 constexpr int G_UNIT = 64;           // global table sizes are multiples of this
 constexpr uint32_t VAL_INF = 0xFFFFFFFFu;
 
@@ -53,6 +76,13 @@ template <> struct Tri<SSSP_W_F32> {
   }
 };
 
+// Heavy owners of one tier: flag (2n), its exclusive scan pos (2n+1), the
+// owners in order (id), their item counts and its exclusive scan off, and
+// the owner index of every item (map).
+struct HList {
+  int32_t *flag, *pos, *id, *items, *off, *map;
+};
+
 struct TbArgs {
   const int32_t *row_ptr;
   const int32_t *col;
@@ -62,22 +92,23 @@ struct TbArgs {
   int rep;          // R: replicas of every column counter (spreads hub contention)
   int32_t *src;     // m: tail of every arc
   int32_t *cnt;     // n*R: in-degree replicas
-  int32_t *cptr;    // n*R+1: CSC offsets (column x starts at cptr[x*R])
+  int32_t *cptr;    // n*R+1: CSC offsets per replica (column x starts at cptr[x*R])
+  int32_t *cb;      // n+1: column x is [cb[x], cb[x+1])
   int32_t *cursor;  // n*R: scatter cursors
-  int2 *cyw;        // m: CSC entries (tail, cost)
-  int32_t *ceid;    // m: CSC -> CSR edge id
-  int2 *ryw;        // m: CSR entries (head, cost), packed copy
+  int2 *cyw;        // m: CSC entries (tail, cost); sorted lists by cost
+  int32_t *ceid;    // m: CSC -> CSR edge id (moves with cyw)
+  int2 *rs;         // m: CSR rows as (head, cost); sorted lists by cost
+  int32_t *sl;      // 2n: lists to sort, short ones from the front, long
+                    //     ones (> SORT_WAVE entries) from the back
   int32_t *work;    // 2n: probes of owner i (i < n: in-table of i; else out-table of i-n)
-  int32_t *hflag;   // 2n: owner i is heavy
-  int32_t *hpos;    // 2n+1: exclusive scan of hflag
-  int32_t *hid;     // heavy owners in order
-  int32_t *hitems;  // items of heavy owner j
-  int32_t *hoff;    // 2n+1: exclusive scan of hitems
+  int32_t *hflag;   // 2n: 0 light, 1 medium, 2 big heavy owner
+  HList hl[2];      // heavy owners: [0] medium, [1] big
   int32_t *gsz;     // 2n: global table size in units of G_UNIT slots (0 = LDS)
   int32_t *goff;    // 2n+1: exclusive scan of gsz
   int32_t *gkey;    // global tables: keys (-1 = empty)
   uint32_t *gval;   //                cheapest parallel arc
-  int32_t *tickets; // [0] heavy items, [1] light owners
+  int32_t *tickets; // [0] / [1] medium / big heavy items, [2] short and
+                    // [3] long lists to sort
   int32_t *status;
   sssp_stats *stats;
 };
@@ -129,14 +160,21 @@ __global__ void k_tb_status(TbArgs a) {
     *a.status = 0;
     a.tickets[0] = 0;
     a.tickets[1] = 0;
+    a.tickets[2] = 0;
+    a.tickets[3] = 0;
   }
   if (a.stats && blockIdx.x == 0 && threadIdx.x < (int)(sizeof(sssp_stats) / 4))
     reinterpret_cast<uint32_t *>(a.stats)[threadIdx.x] = 0u;
 }
 
-__device__ __forceinline__ int cbeg(const TbArgs &a, int x) { return a.cptr[x * a.rep]; }
-__device__ __forceinline__ int clen(const TbArgs &a, int x) {
-  return a.cptr[(x + 1) * a.rep] - a.cptr[x * a.rep];
+__device__ __forceinline__ int cbeg(const TbArgs &a, int x) { return a.cb[x]; }
+__device__ __forceinline__ int clen(const TbArgs &a, int x) { return a.cb[x + 1] - a.cb[x]; }
+
+__global__ void k_tb_cols(TbArgs a) {
+  if (*a.status) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int stride = gridDim.x * blockDim.x;
+  for (int x = t; x <= a.n; x += stride) a.cb[x] = a.cptr[(long long)x * a.rep];
 }
 
 __global__ void k_tb_zero(TbArgs a) {
@@ -151,7 +189,8 @@ __global__ void k_tb_zero(TbArgs a) {
   }
   for (int i = t; i < 2 * a.n; i += stride) {
     a.work[i] = 0;
-    a.hitems[i] = 0;
+    a.hl[0].items[i] = 0;
+    a.hl[1].items[i] = 0;
   }
 }
 
@@ -180,7 +219,7 @@ __global__ void k_tb_indeg(TbArgs a) {
 }
 
 // Thread per arc: scatter into the CSC (each arc into its replica's range)
-// and write the packed CSR copy.
+// and copy the row entries.
 __global__ void k_tb_fill(TbArgs a) {
   if (*a.status) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -193,7 +232,213 @@ __global__ void k_tb_fill(TbArgs a) {
     const int pos = a.cptr[c] + atomicAdd(&a.cursor[c], 1);
     a.cyw[pos] = make_int2(u, (int)wv);
     a.ceid[pos] = e;
-    a.ryw[e] = make_int2(x, (int)wv);
+    a.rs[e] = make_int2(x, (int)wv);
+  }
+}
+
+// ------------------------------------------------------------------ sort
+// List i < n is CSR row i (entries in rs), list n + x is CSC column x
+// (entries in cyw, with ceid carried along).  Sort keys are
+// cost << 32 | vertex: costs are uint32 or the bits of nonnegative floats,
+// which order the same way.
+__device__ __forceinline__ bool sorted_len(int len) { return len > SORT_MIN && len <= SORT_MAX; }
+
+struct SortSeg {
+  int beg, len;
+  bool row;
+};
+
+__device__ __forceinline__ SortSeg sort_seg(const TbArgs &a, int i) {
+  SortSeg g;
+  g.row = i < a.n;
+  if (g.row) {
+    g.beg = a.row_ptr[i];
+    g.len = a.row_ptr[i + 1] - g.beg;
+  } else {
+    g.beg = cbeg(a, i - a.n);
+    g.len = clen(a, i - a.n);
+  }
+  return g;
+}
+
+__device__ __forceinline__ unsigned long long sort_key(const TbArgs &a, const SortSeg &g, int p,
+                                                       int &pay) {
+  const int2 yw = g.row ? a.rs[p] : a.cyw[p];
+  pay = g.row ? 0 : a.ceid[p];
+  return ((unsigned long long)(uint32_t)yw.y << 32) | (uint32_t)yw.x;
+}
+
+__device__ __forceinline__ void sort_put(const TbArgs &a, const SortSeg &g, int p,
+                                         unsigned long long k, int pay) {
+  const int2 yw = make_int2((int)(uint32_t)k, (int)(uint32_t)(k >> 32));
+  if (g.row) {
+    a.rs[p] = yw;
+  } else {
+    a.cyw[p] = yw;
+    a.ceid[p] = pay;
+  }
+}
+
+// Thread per list: queue the lists to sort (two atomics per workgroup pass).
+constexpr int CLS_BS = 1024;
+__global__ __launch_bounds__(CLS_BS) void k_tb_sort_class(TbArgs a) {
+  __shared__ int s_cnt[2][CLS_BS / WAVE];
+  __shared__ int s_base[2];
+  if (*a.status) return;
+  const int lane = lane_id();
+  const int wid = threadIdx.x / WAVE;
+  const int n2 = 2 * a.n;
+  for (int i0 = blockIdx.x * CLS_BS; i0 < n2; i0 += gridDim.x * CLS_BS) {
+    const int i = i0 + threadIdx.x;
+    int len = 0;
+    if (i < n2) len = i < a.n ? a.row_ptr[i + 1] - a.row_ptr[i] : clen(a, i - a.n);
+    const bool srt = sorted_len(len);
+    const bool longl = srt && len > SORT_WAVE;
+    const unsigned long long bs = __ballot(srt && !longl), bl = __ballot(longl);
+    if (lane == 0) {
+      s_cnt[0][wid] = __popcll(bs);
+      s_cnt[1][wid] = __popcll(bl);
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+      int tot = 0;
+      for (int w = 0; w < CLS_BS / WAVE; w++) tot += s_cnt[threadIdx.x][w];
+      s_base[threadIdx.x] = tot ? atomicAdd(&a.tickets[2 + threadIdx.x], tot) : 0;
+    }
+    __syncthreads();
+    int offs = s_base[0], offl = s_base[1];
+    for (int w = 0; w < wid; w++) {
+      offs += s_cnt[0][w];
+      offl += s_cnt[1][w];
+    }
+    const unsigned long long below = (1ull << lane) - 1ull;
+    if (srt && !longl) a.sl[offs + __popcll(bs & below)] = i;
+    if (longl) a.sl[n2 - 1 - (offl + __popcll(bl & below))] = i;
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int j) {
+  const int lo = __shfl_xor((int)(uint32_t)v, j, WAVE);
+  const int hi = __shfl_xor((int)(uint32_t)(v >> 32), j, WAVE);
+  return ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// Bitonic sorting network over 64*R keys (with payloads) held by the wave,
+// element e = lane + 64*r in k[r]; ascending in e.
+template <int R>
+__device__ __forceinline__ void wave_sort(unsigned long long (&k)[R], int (&p)[R]) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int size = 2; size <= WAVE * R; size <<= 1)
+#pragma unroll
+    for (int j = size >> 1; j > 0; j >>= 1) {
+      if (j >= WAVE) {  // both elements of a pair are in this lane
+        const int jr = j / WAVE;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          if (r & jr) continue;
+          const int r2 = r | jr;
+          const bool asc = ((lane + WAVE * r) & size) == 0;
+          if (asc ? k[r2] < k[r] : k[r] < k[r2]) {
+            const unsigned long long tk = k[r];
+            k[r] = k[r2];
+            k[r2] = tk;
+            const int tp = p[r];
+            p[r] = p[r2];
+            p[r2] = tp;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          const int e = lane + WAVE * r;
+          const unsigned long long o = shfl_xor_u64(k[r], j);
+          const int op = __shfl_xor(p[r], j, WAVE);
+          const bool take_min = ((e & j) == 0) == ((e & size) == 0);
+          if (take_min ? o < k[r] : k[r] < o) {
+            k[r] = o;
+            p[r] = op;
+          }
+        }
+      }
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void wave_sort_list(const TbArgs &a, const SortSeg &g) {
+  const int lane = lane_id();
+  unsigned long long k[R];
+  int p[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    const int e = lane + WAVE * r;
+    p[r] = 0;
+    k[r] = e < g.len ? sort_key(a, g, g.beg + e, p[r]) : ~0ull;
+  }
+  wave_sort<R>(k, p);
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    const int e = lane + WAVE * r;
+    if (e < g.len) sort_put(a, g, g.beg + e, k[r], p[r]);
+  }
+}
+
+// One wave per short queued list (SORT_MIN < length <= SORT_WAVE), sorted
+// in registers.
+__global__ void k_tb_sort_small(TbArgs a) {
+  if (*a.status) return;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int nwaves = gridDim.x * blockDim.x / WAVE;
+  const int ns = a.tickets[2];
+  for (int j = wave; j < ns; j += nwaves) {
+    const SortSeg g = sort_seg(a, a.sl[j]);
+    if (g.len <= WAVE) wave_sort_list<1>(a, g);
+    else if (g.len <= 2 * WAVE) wave_sort_list<2>(a, g);
+    else wave_sort_list<4>(a, g);
+  }
+}
+
+// One workgroup per long queued list (SORT_WAVE < length <= SORT_MAX):
+// bitonic sort in LDS, padded to a power of two.  A stage with pair
+// distance <= 64 keeps every wave inside its own 128-key blocks, so two such
+// stages in a row need only a wave barrier.
+__global__ __launch_bounds__(SORT_BS) void k_tb_sort_mid(TbArgs a) {
+  __shared__ unsigned long long sk[SORT_MAX];
+  __shared__ int sp[SORT_MAX];
+  if (*a.status) return;
+  const int tid = threadIdx.x;
+  const int nl = a.tickets[3];
+  for (int j = blockIdx.x; j < nl; j += gridDim.x) {
+    const SortSeg g = sort_seg(a, a.sl[2 * a.n - 1 - j]);
+    int N = 2 * SORT_WAVE;
+    while (N < g.len) N <<= 1;
+    for (int p = tid; p < N; p += SORT_BS) {
+      int pay = 0;
+      sk[p] = p < g.len ? sort_key(a, g, g.beg + p, pay) : ~0ull;
+      sp[p] = pay;
+    }
+    __syncthreads();
+    for (int size = 2; size <= N; size <<= 1)
+      for (int jj = size >> 1; jj > 0; jj >>= 1) {
+        for (int i = tid; i < N / 2; i += SORT_BS) {
+          const int lo = 2 * i - (i & (jj - 1));
+          const int hi = lo + jj;
+          const unsigned long long x = sk[lo], y = sk[hi];
+          if ((x > y) == ((lo & size) == 0)) {
+            sk[lo] = y;
+            sk[hi] = x;
+            const int t = sp[lo];
+            sp[lo] = sp[hi];
+            sp[hi] = t;
+          }
+        }
+        const int next = jj > 1 ? jj >> 1 : size;  // pair distance of the next stage
+        if (jj <= WAVE && next <= WAVE) wave_sync();
+        else __syncthreads();
+      }
+    for (int p = tid; p < g.len; p += SORT_BS) sort_put(a, g, g.beg + p, sk[p], sp[p]);
+    __syncthreads();
   }
 }
 
@@ -263,9 +508,12 @@ __global__ void k_tb_classify(TbArgs a) {
     const int wk = a.work[i];
     const int len = owner_len(a, i);
     const bool heavy = wk > 0 && (len > LT_DEG || wk > LT_WORK);
-    a.hflag[i] = heavy;
+    const bool big = heavy && len > HM_TCAP;
+    a.hflag[i] = heavy ? (big ? 2 : 1) : 0;
+    a.hl[0].flag[i] = heavy && !big;
+    a.hl[1].flag[i] = big;
     int g = 0;
-    if (heavy && len > HV_TCAP) g = (1 << tb_bits(len, 6)) / G_UNIT;
+    if (big && len > HV_TCAP) g = (1 << tb_bits(len, 6)) / G_UNIT;
     a.gsz[i] = g;
   }
 }
@@ -276,22 +524,40 @@ __global__ void k_tb_heavy_list(TbArgs a) {
   const int stride = gridDim.x * blockDim.x;
   for (int i = t; i < 2 * a.n; i += stride)
     if (a.hflag[i]) {
-      const int j = a.hpos[i];
+      const HList &h = a.hl[a.hflag[i] - 1];
+      const int j = h.pos[i];
       const int len = owner_len(a, i);
+      const int cap = len / ITEM_MINQ > 1 ? len / ITEM_MINQ : 1;
       int items = (a.work[i] + HV_TARGET - 1) / HV_TARGET;
-      items = items < 1 ? 1 : (items > len ? len : items);
-      a.hid[j] = i;
-      a.hitems[j] = items;
+      items = items < 1 ? 1 : (items > cap ? cap : items);
+      h.id[j] = i;
+      h.items[j] = items;
     }
+}
+
+// Thread per heavy owner: the owner of each of its items.
+__global__ void k_tb_item_map(TbArgs a) {
+  if (*a.status) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int stride = gridDim.x * blockDim.x;
+  for (int tier = 0; tier < 2; tier++) {
+    const HList &h = a.hl[tier];
+    const int nh = h.pos[2 * a.n];
+    for (int j = t; j < nh; j += stride) {
+      const int o = h.off[j], c = h.items[j];
+      for (int k = 0; k < c; k++) h.map[o + k] = j;
+    }
+  }
 }
 
 // One workgroup per heavy owner with a long list: clear its global table and
 // insert the list (owners are taken in turn from the heavy list).
 __global__ __launch_bounds__(256) void k_tb_gtab(TbArgs a) {
   if (*a.status) return;
-  const int nh = a.hpos[2 * a.n];
+  const HList &h = a.hl[1];
+  const int nh = h.pos[2 * a.n];
   for (int j = blockIdx.x; j < nh; j += gridDim.x) {
-    const int i = a.hid[j];
+    const int i = h.id[j];
     const int g = a.gsz[i];
     if (!g) continue;
     const long long base = (long long)a.goff[i] * G_UNIT;
@@ -311,7 +577,7 @@ __global__ __launch_bounds__(256) void k_tb_gtab(TbArgs a) {
     const int lb = out_list ? a.row_ptr[t] : cbeg(a, t);
     const int ll = out_list ? a.row_ptr[t + 1] - lb : clen(a, t);
     for (int p = threadIdx.x; p < ll; p += blockDim.x) {
-      const int2 yw = out_list ? a.ryw[lb + p] : a.cyw[lb + p];
+      const int2 yw = out_list ? a.rs[lb + p] : a.cyw[lb + p];
       if (yw.x != t) tb_insert(key, val, slots - 1, bits, yw.x, (uint32_t)yw.y);
     }
     __syncthreads();
@@ -344,13 +610,14 @@ __device__ __forceinline__ Owner make_owner(const TbArgs &a, int i) {
 // Table entry of list position p (middle vertex y, its cost); -1 = skipped
 // (the owner's own self-loop is never a middle).
 __device__ __forceinline__ int list_key(const TbArgs &a, const Owner &o, int p, uint32_t &v) {
-  const int2 yw = o.mode ? a.ryw[p] : a.cyw[p];
+  const int2 yw = o.mode ? a.rs[p] : a.cyw[p];
   v = (uint32_t)yw.y;
   return yw.x == o.t ? -1 : yw.x;
 }
 
-// Query at list position p: scanned list [beg, beg+len), arc cost W, arc id
-// and the arc's other end.  len = 0 when the arc belongs to the other side.
+// The arc at position p of the owner's list: the list to scan
+// [beg, beg+len) (len = 0 when the arc belongs to the other side), its cost
+// W, its id and its other end.
 struct Query {
   int beg, len;
   uint32_t W;
@@ -369,239 +636,276 @@ __device__ __forceinline__ Query make_query(const TbArgs &a, const Owner &o, int
     q.eid = a.ceid[p];
     q.other = u;
   } else {  // arc (u = t -> x): scan N_in(x) when |N_in(x)| < |N_out(u)|
-    const int2 xw = a.ryw[p];
-    const int x = xw.x;
+    const int x = a.col[p];
     const int cs = cbeg(a, x), ix = clen(a, x);
     q.beg = cs;
     q.len = o.llen <= ix ? 0 : ix;
-    q.W = (uint32_t)xw.y;
+    q.W = a.w[p];
     q.eid = p;
     q.other = x;
   }
   return q;
 }
 
-// Scanned element f of a query: middle y and the cost of its half of the
-// detour; false when y may not serve as a witness.
-__device__ __forceinline__ bool scan_elem(const TbArgs &a, const Owner &o, int other, int f,
-                                          int &y, uint32_t &wa) {
-  int u, x;
-  const int2 yw = o.mode == 0 ? a.ryw[f] : a.cyw[f];
-  y = yw.x;
-  wa = (uint32_t)yw.y;
-  if (o.mode == 0) {  // element of N_out(u): arc u -> y
-    u = other;
-    x = o.t;
-  } else {  // element of N_in(x): arc y -> x
-    u = o.t;
-    x = other;
+// Examines the scanned entry yw (middle y, its cost) at list position f
+// for arc eid (cost W, other end `other`): 0 = go on, STEP_STOP = the list
+// is sorted and has reached costs >= W at f (entries from f on cannot
+// help), STEP_HIT = a witness was found and the arc is marked.
+constexpr int STEP_STOP = 1, STEP_HIT = 2;
+template <int WT>
+__device__ __forceinline__ int tb_check(const TbArgs &a, const Owner &o, int2 yw, int other,
+                                        bool sorted, uint32_t W, int eid, const int32_t *tkey,
+                                        const uint32_t *tval, int tmask, int tbits) {
+  const int y = yw.x;
+  const uint32_t wa = (uint32_t)yw.y;
+  if (sorted && wa >= W) return STEP_STOP;
+  const int u = o.mode == 0 ? other : o.t;
+  const int x = o.mode == 0 ? o.t : other;
+  if (y == u || y == x) return 0;
+  if (a.local && y / a.bsize != u / a.bsize) return 0;
+  const uint32_t wb = tb_probe(tkey, tval, tmask, tbits, y);
+  if (wb != VAL_INF && Tri<WT>::lt(wa, wb, W)) {
+    a.keep[eid] = 0;
+    return STEP_HIT;
   }
-  if (y == u || y == x) return false;
-  if (a.local && y / a.bsize != u / a.bsize) return false;
-  return true;
+  return 0;
 }
 
+// Last q < nq with off[q] <= idx, galloping forward from hint.
+__device__ __forceinline__ int locate(const int32_t *off, int nq, int idx, int &hint) {
+  int qlo = hint, step = 1;
+  while (qlo + step < nq && off[qlo + step] <= idx) {
+    qlo += step;
+    step <<= 1;
+  }
+  int qhi = min(qlo + step, nq) - 1;
+  while (qlo < qhi) {
+    const int mid = (qlo + qhi + 1) >> 1;
+    if (off[mid] <= idx) qlo = mid;
+    else qhi = mid - 1;
+  }
+  hint = qlo;
+  return qlo;
+}
+
+// Scan limit of an arc in LDS: entries at list positions >= limit are not
+// examined.  A cost stop at f lowers it to f (entries before f may still
+// hold the witness and are examined), a witness lowers it to -1.
+__device__ __forceinline__ int ld_lim(const int32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lower_lim(int32_t *p, int step, int f) {
+  if (step) __hip_atomic_fetch_min(p, step == STEP_HIT ? -1 : f, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+constexpr int32_t UNSORTED = (int32_t)0x80000000;  // flag bit in qother
+constexpr int SCAN_U = 4;  // scanned entries loaded ahead per lane
+
+// Examines the flattened entries idx = first, first+step, ... < tot of the
+// staged arcs (LDS arrays of one batch): SCAN_U loads in flight per lane.
+template <int WT>
+__device__ __forceinline__ void scan_entries(const TbArgs &a, const Owner &o, int first,
+                                             int step, int tot, int nq, const int32_t *qoff,
+                                             const int32_t *qcur, int32_t *qlim,
+                                             const int32_t *qother, const uint32_t *qW,
+                                             const int32_t *qeid, const int32_t *tkey,
+                                             const uint32_t *tval, int tmask, int tbits) {
+  const int2 *list = o.mode == 0 ? a.rs : a.cyw;
+  int hint = 0;
+  for (int base = first; base < tot; base += SCAN_U * step) {
+    int q[SCAN_U], f[SCAN_U];
+    int2 yw[SCAN_U];
+#pragma unroll
+    for (int u = 0; u < SCAN_U; u++) {
+      const int idx = base + u * step;
+      f[u] = -1;
+      q[u] = 0;
+      if (idx < tot) {
+        q[u] = locate(qoff, nq, idx, hint);
+        const int fu = qcur[q[u]] + (idx - qoff[q[u]]);
+        if (fu < ld_lim(&qlim[q[u]])) {
+          f[u] = fu;
+          yw[u] = list[fu];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < SCAN_U; u++) {
+      if (f[u] < 0 || f[u] >= ld_lim(&qlim[q[u]])) continue;
+      const int oth = qother[q[u]];
+      lower_lim(&qlim[q[u]], tb_check<WT>(a, o, yw[u], oth & 0x7FFFFFFF, oth >= 0, qW[q[u]],
+                                          qeid[q[u]], tkey, tval, tmask, tbits), f[u]);
+    }
+  }
+}
+
+template <int SLOTS, int QN>
 struct TbHeavy {
-  int32_t key[HV_SLOTS];
-  uint32_t val[HV_SLOTS];
-  int32_t qbeg[HV_Q];
-  int32_t qoff[HV_Q + 1];
-  uint32_t qW[HV_Q];
-  int32_t qeid[HV_Q];
-  int32_t qother[HV_Q];
+  int32_t key[SLOTS];
+  uint32_t val[SLOTS];
+  int32_t qcur[QN];    // next list position to scan
+  int32_t qoff[QN + 1];
+  uint32_t qW[QN];
+  int32_t qeid[QN];
+  int32_t qother[QN];  // other end | UNSORTED
+  int32_t qlim[QN];    // scan limit
 };
-struct TbLight {
-  int32_t key[TB_NW][LT_SLOTS];
-  uint32_t val[TB_NW][LT_SLOTS];
-  int32_t qbeg[TB_NW][WAVE];
-  int32_t qoff[TB_NW][WAVE + 1];
-  uint32_t qW[TB_NW][WAVE];
-  int32_t qeid[TB_NW][WAVE];
-  int32_t qother[TB_NW][WAVE];
-};
-union TbShared {
-  TbHeavy h;
-  TbLight l;
+struct TbLight {         // one per wave
+  int32_t key[LT_SLOTS];
+  uint32_t val[LT_SLOTS];
+  int32_t qcur[WAVE];
+  int32_t qoff[WAVE + 1];
+  uint32_t qW[WAVE];
+  int32_t qeid[WAVE];
+  int32_t qother[WAVE];
+  int32_t qlim[WAVE];
 };
 
-template <int WT>
-__global__ __launch_bounds__(TB_BS) void k_tb_main(TbArgs a) {
-  __shared__ TbShared sh;
-  __shared__ int s_ws[TB_NW + 1];
+// Heavy owners of one tier: workgroup items taken from a ticket counter;
+// the owner's table is in LDS (SLOTS slots) or, for the longest lists of
+// the big tier, in global memory.
+template <int WT, int TIER, int BS, int SLOTS, int QN>
+__global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
+  __shared__ TbHeavy<SLOTS, QN> H;
+  __shared__ int s_ws[BS / WAVE + 1];
   __shared__ int s_t;
   if (*a.status) return;
   const int tid = threadIdx.x;
-  const int lane = lane_id();
-  const int wid = tid / WAVE;
-  const int nh = a.hpos[2 * a.n];
-  const int total = a.hoff[nh];
+  const HList &hl = a.hl[TIER];
+  const int nh = hl.pos[2 * a.n];
+  const int total = hl.off[nh];
   unsigned long long probes = 0;
-
-  // ---------------------------------------------------------- heavy items
   for (;;) {
-    if (tid == 0) s_t = atomicAdd(&a.tickets[0], 1);
+    if (tid == 0) s_t = atomicAdd(&a.tickets[TIER], 1);
     __syncthreads();
     const int it = s_t;
     __syncthreads();
     if (it >= total) break;
-    int lo = 0, hi = nh - 1;  // last j with hoff[j] <= it
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (a.hoff[mid] <= it) lo = mid;
-      else hi = mid - 1;
-    }
-    const int i = a.hid[lo];
-    const int k = it - a.hoff[lo];
-    const int ni = a.hitems[lo];
+    const int j = hl.map[it];
+    const int i = hl.id[j];
+    const int k = it - hl.off[j];
+    const int ni = hl.items[j];
     const Owner o = make_owner(a, i);
     const int32_t *tkey;
     const uint32_t *tval;
     int tbits;
-    if (a.gsz[i]) {
+    if (TIER == 1 && a.gsz[i]) {
       const long long base = (long long)a.goff[i] * G_UNIT;
       tkey = a.gkey + base;
       tval = a.gval + base;
       tbits = tb_bits(a.gsz[i] * G_UNIT / 2, 6);
     } else {
       tbits = tb_bits(o.llen, 6);
-      for (int s = tid; s < (1 << tbits); s += TB_BS) {
-        sh.h.key[s] = -1;
-        sh.h.val[s] = VAL_INF;
+      for (int s = tid; s < (1 << tbits); s += BS) {
+        H.key[s] = -1;
+        H.val[s] = VAL_INF;
       }
       __syncthreads();
-      for (int p = tid; p < o.llen; p += TB_BS) {
+      for (int p = tid; p < o.llen; p += BS) {
         uint32_t v;
         const int y = list_key(a, o, o.lbeg + p, v);
-        if (y >= 0) tb_insert(sh.h.key, sh.h.val, (1 << tbits) - 1, tbits, y, v);
+        if (y >= 0) tb_insert(H.key, H.val, (1 << tbits) - 1, tbits, y, v);
       }
       __syncthreads();
-      tkey = sh.h.key;
-      tval = sh.h.val;
+      tkey = H.key;
+      tval = H.val;
     }
     const int tmask = (1 << tbits) - 1;
-    // this item's share of the owner's list positions, in rounds of HV_Q
+    // this item's share of the owner's arcs, in batches of QN
     const int p0 = (int)((long long)o.llen * k / ni);
     const int p1 = (int)((long long)o.llen * (k + 1) / ni);
-    for (int r0 = p0; r0 < p1; r0 += HV_Q) {
-      constexpr int EPT = HV_Q / TB_BS;
-      const int nq = min(HV_Q, p1 - r0);
-      int lens[EPT];
-      int lsum = 0;
-#pragma unroll
-      for (int j = 0; j < EPT; j++) {
-        const int qk = tid * EPT + j;
-        lens[j] = 0;
-        if (qk < nq) {
-          const Query q = make_query(a, o, o.lbeg + r0 + qk);
-          sh.h.qbeg[qk] = q.beg;
-          sh.h.qW[qk] = q.W;
-          sh.h.qeid[qk] = q.eid;
-          sh.h.qother[qk] = q.other;
-          lens[j] = q.len;
-        }
-        lsum += lens[j];
+    for (int r0 = p0; r0 < p1; r0 += QN) {
+      const int nq = min(QN, p1 - r0);
+      if (tid < nq) {
+        const Query q = make_query(a, o, o.lbeg + r0 + tid);
+        H.qcur[tid] = q.beg;
+        H.qlim[tid] = q.beg + q.len;
+        H.qW[tid] = q.W;
+        H.qeid[tid] = q.eid;
+        H.qother[tid] = q.other | (sorted_len(q.len) ? 0 : UNSORTED);
       }
-      int tot;
-      int run = block_excl_scan<TB_BS>(lsum, s_ws, &tot);
-#pragma unroll
-      for (int j = 0; j < EPT; j++) {
-        const int qk = tid * EPT + j;
-        if (qk < nq) sh.h.qoff[qk] = run;
-        run += lens[j];
-      }
-      if (tid == 0) sh.h.qoff[nq] = tot;
       __syncthreads();
-      int hint = 0;
-      for (int idx = tid; idx < tot; idx += TB_BS) {
-        int qlo = hint, step = 1;  // last q with qoff[q] <= idx
-        while (qlo + step < nq && sh.h.qoff[qlo + step] <= idx) {
-          qlo += step;
-          step <<= 1;
-        }
-        int qhi = min(qlo + step, nq) - 1;
-        while (qlo < qhi) {
-          const int mid = (qlo + qhi + 1) >> 1;
-          if (sh.h.qoff[mid] <= idx) qlo = mid;
-          else qhi = mid - 1;
-        }
-        hint = qlo;
-        const int f = sh.h.qbeg[qlo] + (idx - sh.h.qoff[qlo]);
-        int y;
-        uint32_t wa;
-        if (!scan_elem(a, o, sh.h.qother[qlo], f, y, wa)) continue;
-        const uint32_t wb = tb_probe(tkey, tval, tmask, tbits, y);
-        if (wb != VAL_INF && Tri<WT>::lt(wa, wb, sh.h.qW[qlo])) a.keep[sh.h.qeid[qlo]] = 0;
+      for (int D = Q_D0;; D = min(2 * D, Q_DMAX)) {
+        int c = 0;
+        if (tid < nq) c = max(0, min(D, H.qlim[tid] - H.qcur[tid]));
+        int tot;
+        const int run = block_excl_scan<BS>(c, s_ws, &tot);
+        if (tot == 0) break;
+        if (tid < nq) H.qoff[tid] = run;
+        if (tid == 0) H.qoff[nq] = tot;
+        __syncthreads();
+        scan_entries<WT>(a, o, tid, BS, tot, nq, H.qoff, H.qcur, H.qlim, H.qother, H.qW, H.qeid,
+                         tkey, tval, tmask, tbits);
+        probes += tid == 0 ? (unsigned long long)tot : 0ull;
+        __syncthreads();
+        if (tid < nq) H.qcur[tid] += c;
+        __syncthreads();
       }
-      probes += tid == 0 ? (unsigned long long)tot : 0ull;
-      __syncthreads();
     }
+    __syncthreads();
   }
+  if (a.stats && tid == 0 && probes) stat_add(&a.stats->wedges, probes);
+}
 
-  // -------------------------------------------- light owners, one per wave
-  int32_t *key = sh.l.key[wid];
-  uint32_t *val = sh.l.val[wid];
-  for (;;) {
-    int i0 = 0;
-    if (lane == 0) i0 = atomicAdd(&a.tickets[1], WAVE);
-    i0 = __shfl(i0, 0, WAVE);
-    if (i0 >= 2 * a.n) break;
-    const int i1 = min(2 * a.n, i0 + WAVE);
+// Light owners: one wave per owner, a private LDS table; owners are dealt
+// to the waves in fixed chunks.
+template <int WT>
+__global__ __launch_bounds__(LT_BS) void k_tb_light(TbArgs a) {
+  __shared__ TbLight sw[LT_BS / WAVE];
+  if (*a.status) return;
+  const int lane = lane_id();
+  TbLight &L = sw[threadIdx.x / WAVE];
+  const int gw = (blockIdx.x * LT_BS + threadIdx.x) / WAVE;
+  const int nw = gridDim.x * (LT_BS / WAVE);
+  unsigned long long probes = 0;
+  for (int i0 = gw * LT_CHUNK; i0 < 2 * a.n; i0 += nw * LT_CHUNK) {
+    const int i1 = min(2 * a.n, i0 + LT_CHUNK);
     for (int i = i0; i < i1; i++) {
       if (a.hflag[i] || a.work[i] == 0) continue;
       const Owner o = make_owner(a, i);
       const int tbits = tb_bits(o.llen, 5);
       const int tmask = (1 << tbits) - 1;
       for (int s = lane; s < (1 << tbits); s += WAVE) {
-        key[s] = -1;
-        val[s] = VAL_INF;
+        L.key[s] = -1;
+        L.val[s] = VAL_INF;
       }
       wave_sync();
       for (int p = lane; p < o.llen; p += WAVE) {
         uint32_t v;
         const int y = list_key(a, o, o.lbeg + p, v);
-        if (y >= 0) tb_insert(key, val, tmask, tbits, y, v);
+        if (y >= 0) tb_insert(L.key, L.val, tmask, tbits, y, v);
       }
       wave_sync();
       for (int r0 = 0; r0 < o.llen; r0 += WAVE) {
         const int nq = min(WAVE, o.llen - r0);
-        int len = 0;
+        int mycur = 0;
         if (lane < nq) {
           const Query q = make_query(a, o, o.lbeg + r0 + lane);
-          sh.l.qbeg[wid][lane] = q.beg;
-          sh.l.qW[wid][lane] = q.W;
-          sh.l.qeid[wid][lane] = q.eid;
-          sh.l.qother[wid][lane] = q.other;
-          len = q.len;
+          mycur = q.beg;
+          L.qlim[lane] = q.beg + q.len;
+          L.qW[lane] = q.W;
+          L.qeid[lane] = q.eid;
+          L.qother[lane] = q.other | (sorted_len(q.len) ? 0 : UNSORTED);
         }
-        const int incl = wave_incl_scan(len);
-        sh.l.qoff[wid][lane] = incl - len;
-        const int tot = __shfl(incl, WAVE - 1, WAVE);
-        if (lane == 0) sh.l.qoff[wid][nq] = tot;
         wave_sync();
-        int hint = 0;
-        for (int idx = lane; idx < tot; idx += WAVE) {
-          int qlo = hint, step = 1;
-          while (qlo + step < nq && sh.l.qoff[wid][qlo + step] <= idx) {
-            qlo += step;
-            step <<= 1;
+        for (int D = Q_D0;; D = min(2 * D, Q_DMAX)) {
+          const int c = lane < nq ? max(0, min(D, L.qlim[lane] - mycur)) : 0;
+          const int incl = wave_incl_scan(c);
+          const int tot = __shfl(incl, WAVE - 1, WAVE);
+          if (tot == 0) break;
+          if (lane < nq) {
+            L.qoff[lane] = incl - c;
+            L.qcur[lane] = mycur;
           }
-          int qhi = min(qlo + step, nq) - 1;
-          while (qlo < qhi) {
-            const int mid = (qlo + qhi + 1) >> 1;
-            if (sh.l.qoff[wid][mid] <= idx) qlo = mid;
-            else qhi = mid - 1;
-          }
-          hint = qlo;
-          const int f = sh.l.qbeg[wid][qlo] + (idx - sh.l.qoff[wid][qlo]);
-          int y;
-          uint32_t wa;
-          if (!scan_elem(a, o, sh.l.qother[wid][qlo], f, y, wa)) continue;
-          const uint32_t wb = tb_probe(key, val, tmask, tbits, y);
-          if (wb != VAL_INF && Tri<WT>::lt(wa, wb, sh.l.qW[wid][qlo]))
-            a.keep[sh.l.qeid[wid][qlo]] = 0;
+          if (lane == 0) L.qoff[nq] = tot;
+          wave_sync();
+          scan_entries<WT>(a, o, lane, WAVE, tot, nq, L.qoff, L.qcur, L.qlim, L.qother, L.qW,
+                           L.qeid, L.key, L.val, tmask, tbits);
+          probes += lane == 0 ? (unsigned long long)tot : 0ull;
+          wave_sync();
+          mycur += c;
         }
-        probes += lane == 0 ? (unsigned long long)tot : 0ull;
-        wave_sync();
       }
     }
   }
@@ -646,7 +950,7 @@ __global__ void k_compact(const int32_t *row_ptr, const int32_t *col, const uint
 namespace {
 struct PruneLayout {
   int rep;
-  size_t src, cnt, cptr, cursor, cyw, ceid, ryw, work, hflag, hpos, hid, hitems, hoff, gsz,
+  size_t src, cnt, cptr, cb, cursor, cyw, ceid, rs, sl, work, hflag, hl[2][6], gsz,
       goff, gkey, gval, tmp, misc, pos, total;
 };
 
@@ -673,16 +977,24 @@ PruneLayout prune_layout(int n, int m, bool compact) {
   L.src = take(4ull * m);
   L.cnt = take(4 * nr);
   L.cptr = take(4 * (nr + 1));
+  L.cb = take(4 * ((size_t)n + 1));
   L.cursor = take(4 * nr);
   L.cyw = take(8ull * m);
   L.ceid = take(4ull * m);
-  L.ryw = take(8ull * m);
+  L.rs = take(8ull * m);
+  L.sl = take(4 * n2);
   L.work = take(4 * n2);
   L.hflag = take(4 * n2);
-  L.hpos = take(4 * (n2 + 1));
-  L.hid = take(4 * n2);
-  L.hitems = take(4 * n2);
-  L.hoff = take(4 * (n2 + 1));
+  for (int t = 0; t < 2; t++) {
+    L.hl[t][0] = take(4 * n2);                           // flag
+    L.hl[t][1] = take(4 * (n2 + 1));                     // pos
+    L.hl[t][2] = take(4 * n2);                           // id
+    L.hl[t][3] = take(4 * n2);                           // items
+    L.hl[t][4] = take(4 * (n2 + 1));                     // off
+    // map: an owner has at most max(1, len / ITEM_MINQ) items and the lists
+    // hold 2m entries in all
+    L.hl[t][5] = take(4 * (n2 + 2ull * (size_t)m / ITEM_MINQ + 64));
+  }
   L.gsz = take(4 * n2);
   L.goff = take(4 * (n2 + 1));
   L.gkey = take(4 * gslots);
@@ -695,6 +1007,20 @@ PruneLayout prune_layout(int n, int m, bool compact) {
   return L;
 }
 }  // namespace
+
+template <typename K>
+void launch_resident(K kernel, int bs, int grid_cus, const TbArgs &a, hipStream_t st) {
+  int per_cu = 0;
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, bs, 0);
+  hipLaunchKernelGGL(kernel, dim3(grid_cus * (per_cu > 0 ? per_cu : 1)), dim3(bs), 0, st, a);
+}
+
+template <int WT>
+void launch_scan_kernels(const TbArgs &a, int grid_cus, hipStream_t st) {
+  launch_resident(k_tb_light<WT>, LT_BS, grid_cus, a, st);
+  launch_resident(k_tb_heavy<WT, 0, HM_BS, HM_SLOTS, HM_Q>, HM_BS, grid_cus, a, st);
+  launch_resident(k_tb_heavy<WT, 1, TB_BS, HV_SLOTS, HV_Q>, TB_BS, grid_cus, a, st);
+}
 
 size_t prune_ws_bytes(int n, int m, bool compact) { return prune_layout(n, m, compact).total; }
 
@@ -717,16 +1043,23 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   a.src = reinterpret_cast<int32_t *>(ws + L.src);
   a.cnt = reinterpret_cast<int32_t *>(ws + L.cnt);
   a.cptr = reinterpret_cast<int32_t *>(ws + L.cptr);
+  a.cb = reinterpret_cast<int32_t *>(ws + L.cb);
   a.cursor = reinterpret_cast<int32_t *>(ws + L.cursor);
   a.cyw = reinterpret_cast<int2 *>(ws + L.cyw);
   a.ceid = reinterpret_cast<int32_t *>(ws + L.ceid);
-  a.ryw = reinterpret_cast<int2 *>(ws + L.ryw);
+  a.rs = reinterpret_cast<int2 *>(ws + L.rs);
+  a.sl = reinterpret_cast<int32_t *>(ws + L.sl);
   a.work = reinterpret_cast<int32_t *>(ws + L.work);
   a.hflag = reinterpret_cast<int32_t *>(ws + L.hflag);
-  a.hpos = reinterpret_cast<int32_t *>(ws + L.hpos);
-  a.hid = reinterpret_cast<int32_t *>(ws + L.hid);
-  a.hitems = reinterpret_cast<int32_t *>(ws + L.hitems);
-  a.hoff = reinterpret_cast<int32_t *>(ws + L.hoff);
+  for (int t = 0; t < 2; t++) {
+    HList &h = a.hl[t];
+    h.flag = reinterpret_cast<int32_t *>(ws + L.hl[t][0]);
+    h.pos = reinterpret_cast<int32_t *>(ws + L.hl[t][1]);
+    h.id = reinterpret_cast<int32_t *>(ws + L.hl[t][2]);
+    h.items = reinterpret_cast<int32_t *>(ws + L.hl[t][3]);
+    h.off = reinterpret_cast<int32_t *>(ws + L.hl[t][4]);
+    h.map = reinterpret_cast<int32_t *>(ws + L.hl[t][5]);
+  }
   a.gsz = reinterpret_cast<int32_t *>(ws + L.gsz);
   a.goff = reinterpret_cast<int32_t *>(ws + L.goff);
   a.gkey = reinterpret_cast<int32_t *>(ws + L.gkey);
@@ -746,25 +1079,26 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   hipLaunchKernelGGL(k_tb_tails, dim3(blocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_tb_indeg, dim3(blocks), dim3(256), 0, st, a);
   if (launch_excl_scan(a.cnt, n * L.rep, a.cptr, tmp, st) != hipSuccess) return SSSP_ERR_HIP;
+  hipLaunchKernelGGL(k_tb_cols, dim3(blocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_tb_fill, dim3(blocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_tb_sort_class, dim3(grid_cus), dim3(CLS_BS), 0, st, a);
+  hipLaunchKernelGGL(k_tb_sort_small, dim3(blocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_tb_sort_mid, dim3(grid_cus * 8), dim3(SORT_BS), 0, st, a);
   hipLaunchKernelGGL(k_tb_work, dim3(blocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_tb_classify, dim3(blocks), dim3(256), 0, st, a);
-  if (launch_excl_scan(a.hflag, 2 * n, a.hpos, tmp, st) != hipSuccess) return SSSP_ERR_HIP;
+  for (int t = 0; t < 2; t++)
+    if (launch_excl_scan(a.hl[t].flag, 2 * n, a.hl[t].pos, tmp, st) != hipSuccess)
+      return SSSP_ERR_HIP;
   if (launch_excl_scan(a.gsz, 2 * n, a.goff, tmp, st) != hipSuccess) return SSSP_ERR_HIP;
   hipLaunchKernelGGL(k_tb_heavy_list, dim3(blocks), dim3(256), 0, st, a);
-  if (launch_excl_scan(a.hitems, 2 * n, a.hoff, tmp, st) != hipSuccess) return SSSP_ERR_HIP;
+  for (int t = 0; t < 2; t++)
+    if (launch_excl_scan(a.hl[t].items, 2 * n, a.hl[t].off, tmp, st) != hipSuccess)
+      return SSSP_ERR_HIP;
+  hipLaunchKernelGGL(k_tb_item_map, dim3(blocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_tb_gtab, dim3(grid_cus * 4), dim3(256), 0, st, a);
-  int per_cu = 0;
   if (ev_start && hipEventRecord((hipEvent_t)ev_start, st) != hipSuccess) return SSSP_ERR_HIP;
-  if (g.wtype == SSSP_W_U32) {
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tb_main<SSSP_W_U32>, TB_BS, 0);
-    hipLaunchKernelGGL(k_tb_main<SSSP_W_U32>, dim3(grid_cus * (per_cu > 0 ? per_cu : 1)),
-                       dim3(TB_BS), 0, st, a);
-  } else {
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tb_main<SSSP_W_F32>, TB_BS, 0);
-    hipLaunchKernelGGL(k_tb_main<SSSP_W_F32>, dim3(grid_cus * (per_cu > 0 ? per_cu : 1)),
-                       dim3(TB_BS), 0, st, a);
-  }
+  if (g.wtype == SSSP_W_U32) launch_scan_kernels<SSSP_W_U32>(a, grid_cus, st);
+  else launch_scan_kernels<SSSP_W_F32>(a, grid_cus, st);
   if (hipGetLastError() != hipSuccess) return SSSP_ERR_HIP;
   if (ev_stop && hipEventRecord((hipEvent_t)ev_stop, st) != hipSuccess) return SSSP_ERR_HIP;
   hipLaunchKernelGGL(k_tb_count_pruned, dim3(512), dim3(256), 0, st, keep, m, stats, a.status);
