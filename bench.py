@@ -455,6 +455,7 @@ def main():
             "roofline": dom,
             "solve_only_gteps": round(head["solve_only_gteps"], 4),
             "prune_ms": round(head["prune_ms"], 4), "solve_ms": round(head["solve_ms"], 4),
+            "trials": head["trials"],
             "roofline_solve": head["roofline_solve"], "roofline_prune": head["roofline_prune"],
             "solve_stats": head["stats"],
         })

@@ -86,9 +86,15 @@ enum {
 };
 
 typedef struct {
-  double delta;            /* bucket width (distance units); 0 = auto;
-                              < 0 or +inf = one unbounded bucket          */
-  int32_t num_partitions;  /* P, 1D blocks of ceil(n/P) vertices; 0 = auto;
+  double delta;            /* bucket width (distance units); < 0 or +inf =
+                              one unbounded bucket; 0 = auto: the autotune
+                              cache entry for this graph's signature, else
+                              computed on the device as a multiple of the
+                              mean of sampled arc costs (0.5x when the
+                              average degree is >= 8, 16x below)          */
+  int32_t num_partitions;  /* P, 1D blocks of ceil(n/P) vertices; 0 = auto
+                              (cache, else blocks of 4096 vertices when the
+                              average degree is >= 8 and 32768 below);
                               raised so that a block has at most 32768 vertices */
   int32_t wg_size;         /* threads per workgroup: 256, 512 or 1024; 0 = auto */
   int32_t num_workgroups;  /* persistent grid size; 0 = auto               */

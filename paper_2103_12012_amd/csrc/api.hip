@@ -110,10 +110,18 @@ unsigned long long delta_units(double delta, int wtype) {
   return b;
 }
 
-double default_delta(int wtype) { return wtype == SSSP_W_U32 ? 128.0 : 1.0; }
+// Defaults when neither the caller nor the autotune cache sets them.  Dense
+// low-diameter graphs (average degree >= 8) take narrow buckets (half the
+// mean arc cost) and 4096-vertex blocks; sparse ones, typically of high
+// diameter with thin frontiers, take wide buckets (16 mean costs) so that a
+// bucket spans many hops, and 32768-vertex blocks.
+static bool dense_graph(int n, long long m) { return n > 0 && m >= 8ll * n; }
 
-int default_parts(int n) {
-  long long p = ((long long)n + 4095) / 4096;
+float auto_delta_factor(int n, long long m) { return dense_graph(n, m) ? 0.5f : 16.0f; }
+
+int default_parts(int n, long long m) {
+  const long long b = dense_graph(n, m) ? 4096 : 32768;
+  long long p = ((long long)n + b - 1) / b;
   if (p < 1) p = 1;
   if (p > 65536) p = 65536;
   return (int)p;
@@ -126,17 +134,21 @@ SolvePlan make_plan(const sssp_csr &g, const sssp_opts &o) {
   if (!(o.flags & SSSP_F_NO_AUTOTUNE) &&
       (o.delta == 0 || o.num_partitions == 0 || o.wg_size == 0 || o.lag == 0))
     have = autotune_lookup(g, &tuned);
-  double delta = o.delta != 0 ? o.delta : (have && tuned.delta != 0 ? tuned.delta
-                                                                     : default_delta(g.wtype));
+  const double delta = o.delta != 0 ? o.delta : (have ? tuned.delta : 0.0);
   int P = o.num_partitions > 0 ? o.num_partitions
                                : (have && tuned.num_partitions > 0 ? tuned.num_partitions
-                                                                   : default_parts(g.n));
+                                                                   : default_parts(g.n, g.m));
   if (P > g.n) P = g.n;
   const int pmin = (int)(((long long)g.n + 32767) / 32768);  // blocks <= 32768 vertices
   if (P < pmin) P = pmin;
   pl.bsize = (g.n + P - 1) / P;
   pl.nparts = (g.n + pl.bsize - 1) / pl.bsize;  // non-empty blocks only
-  pl.delta = delta_units(delta, g.wtype);
+  if (delta != 0) {
+    pl.delta = delta_units(delta, g.wtype);
+  } else {
+    pl.delta = DELTA_AUTO;
+    pl.auto_factor = auto_delta_factor(g.n, g.m);
+  }
   pl.bs = o.wg_size ? o.wg_size : (have && tuned.wg_size ? tuned.wg_size : 256);
   pl.grid = o.num_workgroups ? o.num_workgroups
                              : (have && tuned.num_workgroups ? tuned.num_workgroups : 0);
@@ -223,10 +235,14 @@ int run_solves(std::vector<SolveDesc> &descs, const SolveLayout &L, int nunits, 
   a.max_rounds = o.max_rounds;
   a.num_solves = (int)descs.size();
   a.window = DELTA_INF;
+  a.auto_lag = 0;
   if (descs.size() == 1 && o.lag >= 0 && descs[0].delta != DELTA_INF) {
     const unsigned long long lag = o.lag > 0 ? (unsigned long long)o.lag : 2ull;
-    a.window = window_units(descs[0].delta, lag, wtype);
+    if (descs[0].delta == DELTA_AUTO) a.auto_lag = (int)lag;
+    else a.window = window_units(descs[0].delta, lag, wtype);
   }
+  bool any_auto = false;
+  for (const SolveDesc &d : descs) any_auto = any_auto || d.delta == DELTA_AUTO;
   a.time_limit = time_limit_ticks(g_solve_time_limit_s);
 
   const int ns = (int)descs.size();
@@ -242,6 +258,7 @@ int run_solves(std::vector<SolveDesc> &descs, const SolveLayout &L, int nunits, 
       return SSSP_ERR_HIP;
   }
   if (launch_init(a, ns, max_n, st) != hipSuccess) return SSSP_ERR_HIP;
+  if (any_auto && launch_auto_delta(a, wtype, ns, st) != hipSuccess) return SSSP_ERR_HIP;
   if (o.flags & SSSP_F_VALIDATE)
     for (int i = 0; i < nvalidate; i++)
       if (launch_validate(validate_graphs[i], 0, 0, &a.ctrl->status, st) != hipSuccess)
@@ -302,6 +319,7 @@ extern "C" int sssp_solve(const sssp_csr *g, int32_t source, const sssp_opts *o,
   d.pred = pred;
   d.pred_edge = pred_edge;
   d.delta = pl.delta;
+  d.auto_factor = pl.auto_factor;
   d.n = g->n;
   d.m = g->m;
   d.source = source;
@@ -372,6 +390,7 @@ extern "C" int sssp_solve_batch(int32_t num_graphs, const sssp_csr *graphs, int3
     d.pred = pred ? pred + out_offset[s] : nullptr;
     d.pred_edge = pred_edge ? pred_edge + out_offset[s] : nullptr;
     d.delta = pl.delta;
+    d.auto_factor = pl.auto_factor;
     d.n = g.n;
     d.m = g.m;
     d.source = solve_source[s];
@@ -414,7 +433,7 @@ extern "C" int sssp_prune(const sssp_csr *g, const sssp_opts *o, uint8_t *keep,
   if ((rc = check_ws(ws, *ws_bytes, need))) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if ((rc = check_sync(opts, st))) return rc;
-  int P = opts.num_partitions > 0 ? opts.num_partitions : default_parts(g->n);
+  int P = opts.num_partitions > 0 ? opts.num_partitions : default_parts(g->n, g->m);
   if (P > g->n) P = g->n;
   const int bsize = (g->n + P - 1) / P;
   const int local = (opts.flags & SSSP_F_PRUNE_LOCAL) ? 1 : 0;

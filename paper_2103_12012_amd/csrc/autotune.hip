@@ -1,10 +1,12 @@
-// autotune.hip -- picks delta (bucket width), the partition count P and the
-// workgroup shape for sssp_solve by timing candidates on the device.
+// autotune.hip -- picks delta (bucket width), the partition count P, the
+// lag window and the workgroup size for sssp_solve by timing settings on the
+// device, one coordinate at a time (delta over multiples of the mean arc
+// cost sampled from the device and one unbounded bucket; then P around its
+// default; then lag; then the workgroup size).
 //
 // The bucket width trades the two effects the paper's related-work section
 // describes for delta-stepping: a wide bucket exposes more parallel work per
-// round but re-relaxes more vertices, a narrow one needs more rounds.  The
-// candidates are multiples of the mean arc cost (sampled from the device).
+// round but re-relaxes more vertices, a narrow one needs more rounds.
 // Results are cached per device and coarse graph signature in the process and
 // can be persisted as JSON; solves with automatic options consult the cache.
 #include <algorithm>
@@ -102,46 +104,6 @@ void save_json(const char *path) {
   std::fclose(f);
 }
 
-struct Candidate {
-  double delta;
-  int parts, wg, lag;
-};
-
-// Candidates around the defaults; fields the caller fixed in *best are kept.
-std::vector<Candidate> candidates(const sssp_csr &g, double mean_w, const sssp_opts &fixed) {
-  std::vector<double> deltas;
-  if (fixed.delta != 0) {
-    deltas.push_back(fixed.delta);
-  } else {
-    for (double f : {0.25, 0.5, 1.0, 2.0, 8.0, 32.0}) deltas.push_back(mean_w * f);
-    deltas.push_back(-1.0);  // one unbounded bucket: asynchronous Bellman-Ford
-  }
-  std::vector<int> parts;
-  if (fixed.num_partitions > 0) {
-    parts.push_back(fixed.num_partitions);
-  } else {
-    const int p0 = default_parts(g.n);
-    for (int p : {p0 / 4, p0, p0 * 4}) {
-      int q = std::max(1, std::min(p, g.n));
-      if (std::find(parts.begin(), parts.end(), q) == parts.end()) parts.push_back(q);
-    }
-  }
-  std::vector<int> wgs;
-  if (fixed.wg_size) wgs.push_back(fixed.wg_size);
-  else wgs = {256, 512};
-  std::vector<int> lags;
-  if (fixed.lag) lags.push_back(fixed.lag);
-  else lags = {1, 2, -1};
-  std::vector<Candidate> out;
-  for (double d : deltas)
-    for (int p : parts)
-      for (int w : wgs)
-        for (int l : lags) {
-          if (d < 0 && l != lags[0]) continue;  // no window without buckets
-          out.push_back({d, p, w, l});
-        }
-  return out;
-}
 }  // namespace
 
 bool autotune_lookup(const sssp_csr &g, sssp_opts *out) {
@@ -167,11 +129,11 @@ extern "C" int sssp_autotune(const sssp_csr *g, int32_t source, void *dist_scrat
   // workspace: the largest requirement over the candidate partition counts
   size_t need = 0;
   {
-    const int p0 = best->num_partitions > 0 ? best->num_partitions : default_parts(g->n);
-    for (int p : {p0 / 4, p0, p0 * 4}) {
+    const int p0 = best->num_partitions > 0 ? best->num_partitions : default_parts(g->n, g->m);
+    for (long long p : {(long long)p0 / 4, (long long)p0, (long long)p0 * 4}) {
       sssp_opts o;
       sssp_opts_init(&o);
-      o.num_partitions = std::max(1, std::min(p, g->n));
+      o.num_partitions = (int)std::max(1ll, std::min(p, (long long)g->n));
       o.flags = SSSP_F_NO_AUTOTUNE;
       size_t b = 0;
       if ((rc = sssp_solve(g, source, &o, nullptr, nullptr, nullptr, nullptr, nullptr, &b,
@@ -216,59 +178,86 @@ extern "C" int sssp_autotune(const sssp_csr *g, int32_t source, void *dist_scrat
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return SSSP_ERR_HIP;
-  float best_ms = 1e30f;
-  sssp_opts best_o;
-  sssp_opts_init(&best_o);
-  bool found = false;
+  struct Cleanup {
+    hipEvent_t a, b;
+    ~Cleanup() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+      g_solve_time_limit_s = 30.0;
+    }
+  } cleanup{e0, e1};
   const sssp_opts fixed = *best;
-  struct LimitGuard {
-    ~LimitGuard() { g_solve_time_limit_s = 30.0; }
-  } guard;
-  for (const Candidate &c : candidates(*g, mean_w, fixed)) {
-    // a candidate slower than 4x the best so far stops at the time limit
+  sssp_opts cur;  // the best so far; fields fixed by the caller never change
+  sssp_opts_init(&cur);
+  cur.delta = fixed.delta != 0 ? fixed.delta : mean_w;
+  cur.num_partitions = fixed.num_partitions > 0 ? fixed.num_partitions
+                                                : default_parts(g->n, g->m);
+  cur.wg_size = fixed.wg_size ? fixed.wg_size : 256;
+  cur.lag = fixed.lag ? fixed.lag : 2;
+  cur.num_workgroups = fixed.num_workgroups;
+  float best_ms = 1e30f;
+  bool found = false;
+  // Times one setting (best of two runs); a setting slower than 4x the best
+  // so far is cut short by the device time limit and skipped.
+  auto trial = [&](const sssp_opts &cand) -> int {
     g_solve_time_limit_s = found ? std::min(30.0, std::max(0.02, 4e-3 * best_ms)) : 30.0;
-    sssp_opts o;
-    sssp_opts_init(&o);
-    o.delta = c.delta;
-    o.num_partitions = c.parts;
-    o.wg_size = c.wg;
-    o.lag = c.lag;
-    o.num_workgroups = fixed.num_workgroups;
-    o.flags = SSSP_F_NO_AUTOTUNE;
+    sssp_opts o = cand;
+    o.flags = SSSP_F_NO_AUTOTUNE | SSSP_F_SYNC;
     o.event_start = e0;
     o.event_stop = e1;
     float ms_min = 1e30f;
-    bool ok = true;
-    for (int rep = 0; rep < 2 && ok; rep++) {
+    for (int rep = 0; rep < 2; rep++) {
       size_t b = *ws_bytes;
-      o.flags = SSSP_F_NO_AUTOTUNE | SSSP_F_SYNC;
-      rc = sssp_solve(g, source, &o, dist_scratch, nullptr, nullptr, nullptr, ws, &b, stream);
-      if (rc == SSSP_ERR_TIMEOUT && found) {  // slower than the best: skip it
-        rc = SSSP_OK;
-        ok = false;
-        break;
-      }
-      if (rc != SSSP_OK) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        return rc;
-      }
+      const int r = sssp_solve(g, source, &o, dist_scratch, nullptr, nullptr, nullptr, ws, &b,
+                               stream);
+      if (r == SSSP_ERR_TIMEOUT && found) return SSSP_OK;
+      if (r != SSSP_OK) return r;
       float ms = 0;
-      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-        ok = false;
-        break;
-      }
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return SSSP_ERR_HIP;
       ms_min = std::min(ms_min, ms);
     }
-    if (ok && ms_min < best_ms) {
+    if (ms_min < best_ms) {
       best_ms = ms_min;
-      best_o = o;
+      cur = cand;
       found = true;
     }
+    return SSSP_OK;
+  };
+  // coordinate descent: bucket width, then partitions, lag, workgroup size
+  if ((rc = trial(cur))) return rc;
+  if (fixed.delta == 0) {
+    const sssp_opts base = cur;
+    for (double f : {0.25, 0.5, 2.0, 4.0, 8.0, 16.0, 32.0, 64.0, -1.0}) {
+      sssp_opts c = base;
+      c.delta = f < 0 ? -1.0 : mean_w * f;
+      if ((rc = trial(c))) return rc;
+    }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  if (fixed.num_partitions == 0) {
+    const sssp_opts base = cur;
+    for (int k : {-2, -1, 1, 2}) {
+      sssp_opts c = base;
+      const long long p = k < 0 ? base.num_partitions >> -k : (long long)base.num_partitions << k;
+      c.num_partitions = (int)std::max(1ll, std::min(p, (long long)g->n));
+      if (c.num_partitions == base.num_partitions) continue;
+      if ((rc = trial(c))) return rc;
+    }
+  }
+  if (fixed.lag == 0 && cur.delta > 0) {
+    const sssp_opts base = cur;
+    for (int l : {1, 4, -1}) {
+      sssp_opts c = base;
+      c.lag = l;
+      if ((rc = trial(c))) return rc;
+    }
+  }
+  if (fixed.wg_size == 0) {
+    sssp_opts c = cur;
+    c.wg_size = 512;
+    if ((rc = trial(c))) return rc;
+  }
   if (!found) return SSSP_ERR_TIMEOUT;
+  sssp_opts best_o = cur;
   best_o.flags = 0;
   best_o.event_start = nullptr;
   best_o.event_stop = nullptr;

@@ -13,6 +13,7 @@ constexpr int WAVE = 64;
 constexpr uint32_t NONE_EDGE = 0xFFFFFFFFu;
 constexpr unsigned long long LABEL_INF = ~0ull;
 constexpr unsigned long long DELTA_INF = ~0ull;
+constexpr unsigned long long DELTA_AUTO = 0ull;  // bucket width set on the device
 
 // ------------------------------------------------------------ atomics
 // Every datum that several workgroups write or read while a kernel runs is
@@ -163,7 +164,7 @@ struct SolveDesc {
   int32_t nparts, bsize;       // P and the 1D block size ceil(n/P)
   int32_t unit0;               // first scheduling unit (partition) index
   int32_t nwords;              // ceil(n/32)
-  int32_t pad;
+  float auto_factor;           // DELTA_AUTO: width = factor * mean sampled cost
 };
 
 // Device-wide control block living in the workspace.
@@ -172,7 +173,9 @@ struct Ctrl {
   uint32_t done;    // set once the solve has finished or aborted
   int32_t status;   // first device-detected error
   uint32_t nunits;
-  uint32_t pad[11];
+  uint32_t pad0;
+  unsigned long long window;  // bounded lag in dist units (DELTA_INF = none)
+  uint32_t pad[8];
 };
 
 // Kernel arguments of the persistent solve.
@@ -186,8 +189,10 @@ struct SolveArgs {
   int32_t nunits, nabw;        // units, words of abits
   int32_t max_rounds;
   int32_t num_solves;
-  unsigned long long window;      // bounded lag in dist units (DELTA_INF = none)
+  unsigned long long window;      // bounded lag (copied to Ctrl::window)
   unsigned long long time_limit;  // wall-clock ticks
+  int32_t auto_lag;               // > 0: single solve with DELTA_AUTO, window = lag * width
+  int32_t pad;
 };
 
 // Descriptors travel to the device inside kernel arguments (below 4 KiB).

@@ -9,6 +9,7 @@ hipError_t launch_validate(const sssp_csr &g, int need_sorted, int need_positive
                            int32_t *status, hipStream_t st);
 hipError_t launch_write_desc(const DescChunk &c, SolveDesc *table, hipStream_t st);
 hipError_t launch_init(const SolveArgs &a, int nsolves, int max_n, hipStream_t st);
+hipError_t launch_auto_delta(const SolveArgs &a, int wtype, int nsolves, hipStream_t st);
 hipError_t launch_solve(const SolveArgs &a, int wtype, int bs, int grid, hipStream_t st);
 hipError_t launch_epilogue(const SolveArgs &a, int wtype, int nsolves, int max_n,
                            hipStream_t st);

@@ -13,8 +13,9 @@ struct DevInfo {
 struct SolvePlan {
   int nparts = 1, bsize = 1;  // P (non-empty blocks) and block size ceil(n/P)
   int bs = 256, grid = 1;     // workgroup size and persistent grid
-  unsigned long long delta = DELTA_INF;
-  int lag = 0;                // window in buckets (0 = default)
+  unsigned long long delta = DELTA_INF;  // DELTA_AUTO: set on the device
+  float auto_factor = 0.0f;              // for DELTA_AUTO
+  int lag = 0;                           // window in buckets (0 = default)
 };
 
 DevInfo device_info();
@@ -26,8 +27,8 @@ int check_sync(const sssp_opts &o, hipStream_t st);
 int finish_sync(const int32_t *dev_status, hipStream_t st);
 SolvePlan make_plan(const sssp_csr &g, const sssp_opts &o);
 unsigned long long delta_units(double delta, int wtype);
-int default_parts(int n);
-double default_delta(int wtype);
+int default_parts(int n, long long m);
+float auto_delta_factor(int n, long long m);
 
 // Device time limit of one solve launch in seconds (per host thread);
 // sssp_autotune lowers it so that a slow candidate ends early.

@@ -104,6 +104,7 @@ __global__ void k_init_global(SolveArgs a, int nsolves) {
     a.ctrl->done = 0u;
     a.ctrl->status = 0;
     a.ctrl->nunits = (uint32_t)a.nunits;
+    a.ctrl->window = a.window;
   }
   if (a.stats) {
     uint32_t *s = reinterpret_cast<uint32_t *>(a.stats);
@@ -132,6 +133,43 @@ __global__ void k_init(SolveArgs a) {
     const int u = d.unit0 + ps;
     aor(&a.abits[u >> 5], 1u << (u & 31));
   }
+}
+
+// Bucket width of every solve left automatic (one workgroup per solve):
+// auto_factor times the mean of up to 4096 arc costs sampled at a fixed
+// stride; a single solve's lag window follows from it.
+template <int WT>
+__global__ __launch_bounds__(256) void k_auto_delta(SolveArgs a) {
+  __shared__ double s_part[256 / WAVE];
+  SolveDesc *dd = const_cast<SolveDesc *>(a.desc) + blockIdx.x;
+  if (dd->delta != DELTA_AUTO) return;
+  const int m = dd->m;
+  const int k = m < 4096 ? m : 4096;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    const uint32_t w = dd->w[(long long)i * m / k];
+    acc += WT == SSSP_W_U32 ? (double)w : (double)__uint_as_float(w);
+  }
+  for (int o = WAVE / 2; o > 0; o >>= 1) acc += __shfl_down(acc, o, WAVE);
+  if (lane_id() == 0) s_part[threadIdx.x / WAVE] = acc;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double sum = 0.0;
+  for (int i = 0; i < 256 / WAVE; i++) sum += s_part[i];
+  const double width = (double)dd->auto_factor * (k > 0 ? sum / k : 1.0);
+  unsigned long long delta, window = DELTA_INF;
+  if (WT == SSSP_W_U32) {
+    const double c = ceil(width);
+    delta = c < 1.0 ? 1ull : (c >= 4294967296.0 ? DELTA_INF : (unsigned long long)c);
+    if (a.auto_lag > 0 && delta != DELTA_INF) window = delta * (unsigned long long)a.auto_lag;
+  } else {
+    float f = (float)width;
+    if (!(f > 0.0f)) f = 1.17549435e-38f;  // smallest normal
+    delta = f == __builtin_inff() ? DELTA_INF : __float_as_uint(f);
+    if (a.auto_lag > 0 && delta != DELTA_INF) window = __float_as_uint(f * (float)a.auto_lag);
+  }
+  dd->delta = delta;
+  if (a.num_solves == 1) a.ctrl->window = window;
 }
 
 // Bijective 32-bit mix of a unit id (per-workgroup key) used to break ties
@@ -195,6 +233,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
   if (s_exit) return;
 
   const unsigned long long t_start = wall_clock64();
+  const unsigned long long window = a.ctrl->window;  // fixed before the launch
   int rounds = 0;
   int stay = -1;  // unit kept from the previous batch (still holding work)
   uint32_t mixkey = blockIdx.x * 0x85EBCA6Bu;
@@ -269,8 +308,8 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
             act = u < a.nunits && ((ld_rlx(&abits[u >> 5]) >> (u & 31)) & 1u);
             d = act ? ld_rlx(&unit_min[u]) : ~0ull;
           }
-          if (act && (d == ~0ull || gmin == ~0ull || a.window == DELTA_INF ||
-                      Dist<WT>::within(d, gmin, a.window))) {
+          if (act && (d == ~0ull || gmin == ~0ull || window == DELTA_INF ||
+                      Dist<WT>::within(d, gmin, window))) {
             const unsigned long long key = unit_mix((uint32_t)u, mixkey);
             best = key < best ? key : best;
           }
@@ -689,7 +728,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
         // keep the unit while its remaining work is within the lag window of
         // the least pending distance seen at the pick; otherwise (or when it
         // overflowed the frontier) let any workgroup take it
-        if (!trunc && (a.window == DELTA_INF || Dist<WT>::within(rem, s_gmin, a.window)))
+        if (!trunc && (window == DELTA_INF || Dist<WT>::within(rem, s_gmin, window)))
           s_stay = unit;
         else
           aor(&abits[unit >> 5], 1u << (unit & 31));
@@ -808,6 +847,14 @@ hipError_t launch_validate(const sssp_csr &g, int need_sorted, int need_positive
 
 hipError_t launch_write_desc(const DescChunk &c, SolveDesc *table, hipStream_t st) {
   hipLaunchKernelGGL(k_write_desc, dim3(1), dim3(32), 0, st, c, table);
+  return hipGetLastError();
+}
+
+hipError_t launch_auto_delta(const SolveArgs &a, int wtype, int nsolves, hipStream_t st) {
+  if (wtype == SSSP_W_U32)
+    hipLaunchKernelGGL(k_auto_delta<SSSP_W_U32>, dim3(nsolves), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_auto_delta<SSSP_W_F32>, dim3(nsolves), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

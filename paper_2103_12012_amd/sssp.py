@@ -30,6 +30,7 @@ ERRORS = {
     -7: "SSSP_ERR_OVERFLOW", -8: "SSSP_ERR_TIMEOUT", -9: "SSSP_ERR_WORKSPACE",
     -10: "SSSP_ERR_HIP", -11: "SSSP_ERR_CAPTURE", -12: "SSSP_ERR_CYCLE",
 }
+ERR_WORKSPACE = -9
 
 
 class SSSPError(RuntimeError):
@@ -229,12 +230,13 @@ class Solver:
 
     def __init__(self, row_ptr, col, w, *, delta=0.0, num_partitions=0, wg_size=0,
                  num_workgroups=0, max_rounds=0, validate=True, want_pred=True,
-                 stats=False, lag=0):
+                 stats=False, lag=0, no_autotune=False):
         self.g = _csr(row_ptr, col, w)
         self._keep = (row_ptr, col, w)
         self.opts = make_opts(delta, num_partitions, wg_size, num_workgroups, max_rounds,
-                              validate=validate, lag=lag)
+                              validate=validate, lag=lag, no_autotune=no_autotune)
         dev = col.device
+        self.col_device = dev
         n = self.g.n
         self.dist = torch.empty(n, dtype=w.dtype, device=dev)
         self.pred = torch.empty(n, dtype=torch.int32, device=dev) if want_pred else None
@@ -253,11 +255,19 @@ class Solver:
             o.flags = (o.flags | F_VALIDATE) if validate else (o.flags & ~F_VALIDATE)
         if events is not None:
             o.event_start, o.event_stop = events
-        nb = ctypes.c_size_t(self.ws.numel())
-        rc = lib().sssp_solve(ctypes.byref(self.g), int(source), ctypes.byref(o),
-                              _ptr(self.dist), _ptr(self.pred), _ptr(self.pred_edge),
-                              _ptr(self.stats.t) if self.stats else None, _ptr(self.ws),
-                              ctypes.byref(nb), _stream())
+        for attempt in range(2):
+            nb = ctypes.c_size_t(self.ws.numel())
+            rc = lib().sssp_solve(ctypes.byref(self.g), int(source), ctypes.byref(o),
+                                  _ptr(self.dist), _ptr(self.pred), _ptr(self.pred_edge),
+                                  _ptr(self.stats.t) if self.stats else None, _ptr(self.ws),
+                                  ctypes.byref(nb), _stream())
+            if rc != ERR_WORKSPACE or attempt:
+                break
+            # automatic options now resolve differently (the autotune cache
+            # changed since construction): size the workspace again
+            self.ws = _workspace(lambda q: lib().sssp_solve(
+                ctypes.byref(self.g), 0, ctypes.byref(self.opts), None, None, None, None, None,
+                q, None), self.col_device)
         _check(rc, "sssp_solve")
         return self.dist, self.pred, self.pred_edge
 

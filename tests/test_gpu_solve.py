@@ -159,3 +159,46 @@ def test_grid4096_full_size(opts):
     dist, pred, pe = gpu_solve(g, 0, **opts)
     assert oracle.certify(g.row_ptr, g.col, g.w, 0, dist, pe) == (0, -1)
     assert_solve_parity(g, 0, (dist, pred, pe))
+
+
+def _auto_width(g, factor):
+    """Expected automatic bucket width: factor x the mean of the sampled
+    costs (4096 arcs at a fixed stride), rounded up for integer costs."""
+    m = g.m
+    k = min(m, 4096)
+    idx = (np.arange(k, dtype=np.int64) * m) // k
+    mean = g.w[idx].astype(np.float64).mean()
+    return int(np.ceil(factor * mean))
+
+
+@pytest.mark.parametrize("kind", ["dense", "sparse"])
+def test_auto_delta_width_and_parity(kind):
+    """Automatic options (no cache entry): the device picks the bucket width
+    from sampled costs (0.5x the mean at average degree >= 8, 16x below) and
+    the result still equals the oracle."""
+    g = gen.rmat(11, 41) if kind == "dense" else gen.grid(96, 80, seed=9)
+    factor = 0.5 if g.m >= 8 * g.n else 16.0
+    S = sssp_mod()
+    rp, c, w = dev(g)
+    solver = S.Solver(rp, c, w, no_autotune=True, stats=True)
+    s = 0 if kind == "sparse" else int(gen.random_sources(g, 1, 41)[0])
+    dist, pred, pe = solver(s, sync=True)
+    st = solver.stats.read()
+    assert st["delta_bits"] == _auto_width(g, factor)
+    assert_solve_parity(g, s, (dist.cpu().numpy().view(np.uint32), pred.cpu().numpy(),
+                               pe.cpu().numpy()))
+
+
+def test_auto_delta_fp32():
+    g = gen.rmat(10, 42, weight="f32", wlo=0.5, whi=1.5)
+    S = sssp_mod()
+    rp, c, w = dev(g)
+    solver = S.Solver(rp, c, w, no_autotune=True, stats=True)
+    s = int(gen.random_sources(g, 1, 42)[0])
+    dist, pred, pe = solver(s, sync=True)
+    st = solver.stats.read()
+    k = min(g.m, 4096)
+    idx = (np.arange(k, dtype=np.int64) * g.m) // k
+    width = np.float32(0.5 * g.w[idx].astype(np.float64).mean())
+    assert abs(np.uint32(st["delta_bits"]).view(np.float32) - width) <= 1e-6 * width
+    assert_solve_parity(g, s, (dist.cpu().numpy(), pred.cpu().numpy(), pe.cpu().numpy()))
