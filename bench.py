@@ -67,9 +67,12 @@ def m_reached(g, source):
 
 
 KERNEL_SOURCES = {  # files each kernel is compiled from (for the counter-staleness check)
-    "k_tb_main": ("internal.hpp", "prune.hip"),
     "k_solve": ("internal.hpp", "solve.hip"),
+    "k_tb_light": ("internal.hpp", "prune.hip"),
+    "k_tb_heavy_medium": ("internal.hpp", "prune.hip"),
+    "k_tb_heavy_big": ("internal.hpp", "prune.hip"),
 }
+TRISHLA_SCAN = ("k_tb_light", "k_tb_heavy_medium", "k_tb_heavy_big")
 
 
 def kernel_source_hash(kernel):
@@ -107,9 +110,12 @@ def counter_traffic(kernel, workload):
     return int(fetch + write)
 
 
-def roofline(name, bytes_alg, ms, bound="hbm", workload=None):
+def roofline(name, bytes_alg, ms, bound="hbm", workload=None, parts=None):
     gbs = bytes_alg / (ms * 1e-3) / 1e9
-    traffic = counter_traffic(name, workload) if workload else None
+    traffic = None
+    if workload:
+        ts = [counter_traffic(k, workload) for k in (parts or (name,))]
+        traffic = None if any(t is None for t in ts) else sum(ts)
     return {"bound": bound, "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": name,
             "avg_launch_ms": round(ms, 4), "algorithmic_bytes": int(bytes_alg)}
@@ -220,7 +226,8 @@ def bench_rmat20(steps, warmup, cpu_leg=True):
         "n": g.n, "m": g.m, "m_kept": kept_m, "m_cc": mcc, "reached": reached, "source": s,
         "stats": st,
         "roofline_solve": roofline("k_solve", b_solve, solve_ms, workload="rmat20"),
-        "roofline_prune": roofline("k_tb_main", b_prune, prune_ms, workload="rmat20"),
+        "roofline_prune": roofline("k_tb_light+k_tb_heavy", b_prune, prune_ms, workload="rmat20",
+                                   parts=TRISHLA_SCAN),
         "wedges": st.get("wedges"),
     }
     if cpu_leg:

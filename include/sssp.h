@@ -96,8 +96,10 @@ typedef struct {
                               (cache, else blocks of 4096 vertices when the
                               average degree is >= 8 and 32768 below);
                               raised so that a block has at most 32768 vertices */
-  int32_t wg_size;         /* threads per workgroup: 256, 512 or 1024; 0 = auto */
-  int32_t num_workgroups;  /* persistent grid size; 0 = auto               */
+  int32_t wg_size;         /* threads per workgroup: 256, 512 or 1024; 0 = auto
+                              (cache, else 512)                            */
+  int32_t num_workgroups;  /* persistent grid size; 0 = auto (cache, else one
+                              workgroup per CU); capped by residency       */
   int32_t max_rounds;      /* > 0: stop after this many frontier batches per
                               workgroup and report SSSP_ERR_TIMEOUT; the
                               labels are then valid upper bounds           */
@@ -219,7 +221,7 @@ int sssp_backward(const sssp_csr *g, int32_t source, const float *dist,
 
 /* ------------------------------------------------------------ autotune */
 /*
- * Time candidate (delta, num_partitions, wg_size, lag) settings for
+ * Time candidate (delta, num_partitions, wg_size, num_workgroups, lag) settings for
  * sssp_solve on this graph and source and write the fastest into *best
  * (synchronous; not for capture).  *best is in/out: fields the caller sets
  * to nonzero values (delta, num_partitions, wg_size, num_workgroups, lag)

@@ -149,20 +149,21 @@ SolvePlan make_plan(const sssp_csr &g, const sssp_opts &o) {
     pl.delta = DELTA_AUTO;
     pl.auto_factor = auto_delta_factor(g.n, g.m);
   }
-  pl.bs = o.wg_size ? o.wg_size : (have && tuned.wg_size ? tuned.wg_size : 256);
+  pl.bs = o.wg_size ? o.wg_size : (have && tuned.wg_size ? tuned.wg_size : 512);
   pl.grid = o.num_workgroups ? o.num_workgroups
                              : (have && tuned.num_workgroups ? tuned.num_workgroups : 0);
   pl.lag = o.lag ? o.lag : (have ? tuned.lag : 0);
   return pl;
 }
 
-// Persistent grid: the requested size (0 = two workgroups per CU), capped by
-// what can be resident at block size bs.
+// Persistent grid: the requested size (0 = one workgroup per CU), capped by
+// what can be resident at block size bs.  More workgroups than CUs mostly
+// add contention on the shared unit tables and labels.
 int plan_grid(int wtype, int bs, int want) {
   const DevInfo di = device_info();
   const int per_cu = solve_max_blocks_per_cu(wtype, bs);
   const int resident = di.cus * per_cu;
-  if (want <= 0) want = resident;
+  if (want <= 0) want = di.cus;
   int grid = want < resident ? want : resident;
   return grid < 1 ? 1 : grid;
 }

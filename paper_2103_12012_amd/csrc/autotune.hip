@@ -2,7 +2,7 @@
 // lag window and the workgroup size for sssp_solve by timing settings on the
 // device, one coordinate at a time (delta over multiples of the mean arc
 // cost sampled from the device and one unbounded bucket; then P around its
-// default; then lag; then the workgroup size).
+// default; then lag; then the workgroup size; then the grid size).
 //
 // The bucket width trades the two effects the paper's related-work section
 // describes for delta-stepping: a wide bucket exposes more parallel work per
@@ -192,7 +192,7 @@ extern "C" int sssp_autotune(const sssp_csr *g, int32_t source, void *dist_scrat
   cur.delta = fixed.delta != 0 ? fixed.delta : mean_w;
   cur.num_partitions = fixed.num_partitions > 0 ? fixed.num_partitions
                                                 : default_parts(g->n, g->m);
-  cur.wg_size = fixed.wg_size ? fixed.wg_size : 256;
+  cur.wg_size = fixed.wg_size ? fixed.wg_size : 512;
   cur.lag = fixed.lag ? fixed.lag : 2;
   cur.num_workgroups = fixed.num_workgroups;
   float best_ms = 1e30f;
@@ -253,8 +253,17 @@ extern "C" int sssp_autotune(const sssp_csr *g, int32_t source, void *dist_scrat
   }
   if (fixed.wg_size == 0) {
     sssp_opts c = cur;
-    c.wg_size = 512;
+    c.wg_size = 256;
     if ((rc = trial(c))) return rc;
+  }
+  if (fixed.num_workgroups == 0) {
+    const sssp_opts base = cur;
+    const int cus = device_info().cus;
+    for (int gw : {cus / 2, 2 * cus}) {
+      sssp_opts c = base;
+      c.num_workgroups = gw;
+      if ((rc = trial(c))) return rc;
+    }
   }
   if (!found) return SSSP_ERR_TIMEOUT;
   sssp_opts best_o = cur;

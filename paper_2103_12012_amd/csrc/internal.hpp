@@ -167,16 +167,20 @@ struct SolveDesc {
   float auto_factor;           // DELTA_AUTO: width = factor * mean sampled cost
 };
 
-// Device-wide control block living in the workspace.
+// Device-wide control block living in the workspace.  The pending-work
+// counter has a 128-byte line to itself: its atomics do not slow the loads
+// of the flags that every workgroup polls.
 struct Ctrl {
-  long long work;   // pending work: inbox bits + claimed vertices (+ slack)
+  long long work;   // pending work: inbox bits + claimed vertices (+ raises)
+  uint32_t pad_w[30];
   uint32_t done;    // set once the solve has finished or aborted
   int32_t status;   // first device-detected error
   uint32_t nunits;
   uint32_t pad0;
   unsigned long long window;  // bounded lag in dist units (DELTA_INF = none)
-  uint32_t pad[8];
+  uint32_t pad[26];
 };
+static_assert(sizeof(Ctrl) == 256, "Ctrl layout");
 
 // Kernel arguments of the persistent solve.
 struct SolveArgs {

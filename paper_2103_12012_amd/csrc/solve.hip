@@ -32,6 +32,10 @@ namespace sssp_impl {
 constexpr int FCAP = 1024;  // frontier vertices staged in LDS per round
 constexpr int MAXB = 32768; // largest partition (vertices)
 constexpr int MAX_ROUNDS_PER_BATCH = 256;
+// Pending-count raise of one batch: above MAX_ROUNDS_PER_BATCH * (2^31 - 1)
+// inbox bits, and 2^50 per workgroup keeps the sum far from overflow.
+constexpr long long RAISE = 1ll << 50;
+static_assert((long long)MAX_ROUNDS_PER_BATCH * 0x7FFFFFFFll < RAISE, "raise too small");
 
 template <int WT> struct Dist;
 template <> struct Dist<SSSP_W_U32> {
@@ -235,6 +239,8 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
   const unsigned long long t_start = wall_clock64();
   const unsigned long long window = a.ctrl->window;  // fixed before the launch
   int rounds = 0;
+  // counters of this workgroup (thread 0), added to the stats once at exit
+  unsigned long long st_tot = 0, st_upd = 0, st_cross = 0, st_exp = 0, st_batches = 0;
   int stay = -1;  // unit kept from the previous batch (still holding work)
   uint32_t mixkey = blockIdx.x * 0x85EBCA6Bu;
   unsigned long long umv[4], um0[4];
@@ -496,20 +502,24 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
     // partition that land in the current bucket form the next round's
     // frontier in LDS (deduplicated by an LDS bitmap) instead of going
     // through the inbox, so the partition settles its bucket in one batch.
-    // Each round first raises the pending count by m + FCAP, an upper bound
-    // of the inbox bits it can set (thread 0's round trip overlaps the
-    // staging loads); the batch returns the surplus once at the end.
+    // The batch first raises the pending count by RAISE, more than the inbox
+    // bits all its rounds can set (at most m per round, MAX_ROUNDS_PER_BATCH
+    // rounds), and returns the surplus once at the end.
     int cur_cnt = cnt;
     int nround = 0;
     long long raised = 0;  // thread 0 only
     for (;;) {
       if (tid == 0) {
-        // the returned value is consumed so that the add has completed before
-        // thread 0 reaches the barrier below (no inbox bit of this round is
-        // published before that barrier)
-        const long long before = aadd(&ctrl->work, (long long)m + FCAP);
-        raised += (long long)m + FCAP;
-        s_ncnt = before == LLONG_MIN ? 1 : 0;
+        if (nround == 0) {
+          // the returned value is consumed so that the add has completed
+          // before thread 0 reaches the barrier below (no inbox bit of this
+          // batch is published before that barrier)
+          const long long before = aadd(&ctrl->work, RAISE);
+          raised = RAISE;
+          s_ncnt = before == LLONG_MIN ? 1 : 0;
+        } else {
+          s_ncnt = 0;
+        }
       }
       for (int k0 = 0; k0 < cur_cnt; k0 += BS * 4) {
         unsigned long long lab[4];
@@ -733,13 +743,11 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
         else
           aor(&abits[unit >> 5], 1u << (unit & 31));
       }
-      if (a.stats) {
-        stat_add(&a.stats->edges_relaxed, (uint64_t)s_tot);
-        stat_add(&a.stats->label_updates, (uint64_t)s_upd);
-        stat_add(&a.stats->cross_updates, (uint64_t)s_cross);
-        stat_add(&a.stats->vertices_expanded, (uint64_t)s_exp);
-        stat_add(&a.stats->batches, 1);
-      }
+      st_tot += (unsigned long long)s_tot;
+      st_upd += s_upd;
+      st_cross += s_cross;
+      st_exp += (unsigned long long)s_exp;
+      st_batches++;
       if (a.max_rounds > 0 && ++rounds >= a.max_rounds) {
         set_status(&ctrl->status, SSSP_ERR_TIMEOUT);
         st_rlx(&ctrl->done, 1u);
@@ -747,6 +755,13 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
     }
     __syncthreads();
     stay = s_stay;
+  }
+  if (threadIdx.x == 0 && a.stats && st_batches) {
+    stat_add(&a.stats->edges_relaxed, st_tot);
+    stat_add(&a.stats->label_updates, st_upd);
+    stat_add(&a.stats->cross_updates, st_cross);
+    stat_add(&a.stats->vertices_expanded, st_exp);
+    stat_add(&a.stats->batches, st_batches);
   }
 }
 
