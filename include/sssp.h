@@ -229,14 +229,36 @@ int sssp_backward(const sssp_csr *g, int32_t source, const float *dist,
  * arc cost sampled from the device, and one unbounded bucket).  Results
  * are cached in the process, keyed by the device and a signature of the
  * graph (weight type, ceil(log2 n), floor(log2) of the average degree), and
- * sssp_solve / sssp_solve_batch with automatic options consult the cache.
- * If cache_path is non-NULL the cache is loaded from and saved to that JSON
- * file.
+ * sssp_solve with automatic options consults the cache.  If cache_path is
+ * non-NULL the cache is loaded from and saved to that JSON file.  The
+ * bucket-width trade-off it searches is the one the paper's discussion of
+ * delta-stepping describes (wider buckets: more parallel work, more
+ * re-relaxation).
  *   dist_scratch  device buffer of 4*n bytes used as the dist output
  */
 int sssp_autotune(const sssp_csr *g, int32_t source, void *dist_scratch,
                   sssp_opts *best, const char *cache_path, void *ws,
                   size_t *ws_bytes, void *stream);
+
+/*
+ * The same for one sssp_solve_batch call: times settings of the whole
+ * batched launch (delta: each graph's automatic width or one shared
+ * multiple of the mean cost of graphs[0]; num_partitions: each graph's
+ * default or one shared count; wg_size; num_workgroups) and writes the
+ * fastest into *best (in/out as above; lag does not apply to batches).  The
+ * result is cached under a signature of the batch (weight type, number of
+ * graphs and solves, ceil(log2) of the total vertex count, floor(log2) of
+ * the average degree); sssp_solve_batch with automatic options consults only
+ * such batch entries.  Arguments as in sssp_solve_batch, plus:
+ *   dist_scratch  device buffer holding the batch's dist output
+ *                 (4 * max(out_offset[s] + n of solve s) bytes)
+ * Workspace protocol as everywhere (ws == NULL queries the largest
+ * requirement over the candidates).  Synchronous; not for capture.
+ */
+int sssp_autotune_batch(int32_t num_graphs, const sssp_csr *graphs, int32_t num_solves,
+                        const int32_t *solve_graph, const int32_t *solve_source,
+                        const int64_t *out_offset, void *dist_scratch, sssp_opts *best,
+                        const char *cache_path, void *ws, size_t *ws_bytes, void *stream);
 
 /* Library version string. */
 const char *sssp_version(void);

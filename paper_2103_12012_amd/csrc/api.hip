@@ -350,6 +350,18 @@ extern "C" int sssp_solve_batch(int32_t num_graphs, const sssp_csr *graphs, int3
   sssp_opts_init(&opts);
   if (o) opts = *o;
   if ((rc = check_opts(&opts))) return rc;
+  // automatic fields come from the batch's own cache entry (entries tuned
+  // for single solves do not carry over: a batch runs without a lag window)
+  if (!(opts.flags & SSSP_F_NO_AUTOTUNE)) {
+    sssp_opts tuned;
+    if (autotune_lookup_batch(num_graphs, graphs, num_solves, &tuned)) {
+      if (opts.delta == 0) opts.delta = tuned.delta;
+      if (opts.num_partitions == 0) opts.num_partitions = tuned.num_partitions;
+      if (opts.wg_size == 0) opts.wg_size = tuned.wg_size;
+      if (opts.num_workgroups == 0) opts.num_workgroups = tuned.num_workgroups;
+    }
+    opts.flags |= SSSP_F_NO_AUTOTUNE;
+  }
   std::vector<SolvePlan> gplan(num_graphs);
   for (int i = 0; i < num_graphs; i++) gplan[i] = make_plan(graphs[i], opts);
   std::vector<int> ns(num_solves);

@@ -52,6 +52,23 @@ std::string graph_key(const sssp_csr &g) {
          "|log2deg=" + std::to_string(ld);
 }
 
+// Batch signature: weight type, number of graphs and of solves, ceil(log2)
+// of the total vertex count and floor(log2) of the average degree.
+std::string batch_key(int num_graphs, const sssp_csr *graphs, int num_solves) {
+  long long n = 0, m = 0;
+  for (int i = 0; i < num_graphs; i++) {
+    n += graphs[i].n;
+    m += graphs[i].m;
+  }
+  int ln = 0;
+  while ((1ll << ln) < n) ln++;
+  const double avg = m > 0 ? (double)m / (double)n : 0.0;
+  const int ld = avg > 0 ? (int)std::floor(std::log2(avg)) : -99;
+  return device_tag() + "|batch|w=" + std::to_string(graphs[0].wtype) + "|g=" +
+         std::to_string(num_graphs) + "|s=" + std::to_string(num_solves) + "|log2n=" +
+         std::to_string(ln) + "|log2deg=" + std::to_string(ld);
+}
+
 void load_json(const char *path) {
   FILE *f = std::fopen(path, "r");
   if (!f) return;
@@ -110,6 +127,16 @@ bool autotune_lookup(const sssp_csr &g, sssp_opts *out) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (g_cache.empty()) return false;
   auto it = g_cache.find(graph_key(g));
+  if (it == g_cache.end()) return false;
+  *out = it->second;
+  return true;
+}
+
+bool autotune_lookup_batch(int num_graphs, const sssp_csr *graphs, int num_solves,
+                           sssp_opts *out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_cache.empty()) return false;
+  auto it = g_cache.find(batch_key(num_graphs, graphs, num_solves));
   if (it == g_cache.end()) return false;
   *out = it->second;
   return true;
@@ -274,6 +301,153 @@ extern "C" int sssp_autotune(const sssp_csr *g, int32_t source, void *dist_scrat
   {
     std::lock_guard<std::mutex> lk(g_mu);
     g_cache[graph_key(*g)] = best_o;
+    if (cache_path) save_json(cache_path);
+  }
+  return SSSP_OK;
+}
+
+extern "C" int sssp_autotune_batch(int32_t num_graphs, const sssp_csr *graphs, int32_t num_solves,
+                                   const int32_t *solve_graph, const int32_t *solve_source,
+                                   const int64_t *out_offset, void *dist_scratch,
+                                   sssp_opts *best, const char *cache_path, void *ws,
+                                   size_t *ws_bytes, void *stream) {
+  if (!ws_bytes || !best || num_graphs < 1 || !graphs) return SSSP_ERR_ARG;
+  const sssp_opts fixed = *best;
+  // candidate partition counts (0 = each graph's default)
+  std::vector<int> parts;
+  if (fixed.num_partitions > 0) parts = {fixed.num_partitions};
+  else parts = {0, 4, 16, 64};
+  int rc;
+  size_t need = 0;
+  for (int p : parts) {
+    sssp_opts o;
+    sssp_opts_init(&o);
+    o.num_partitions = p;
+    o.flags = SSSP_F_NO_AUTOTUNE;
+    size_t b = 0;
+    if ((rc = sssp_solve_batch(num_graphs, graphs, num_solves, solve_graph, solve_source,
+                               out_offset, &o, nullptr, nullptr, nullptr, nullptr, nullptr, &b,
+                               stream)))
+      return rc;
+    need = std::max(need, b);
+  }
+  if (!ws) {
+    *ws_bytes = need;
+    return SSSP_OK;
+  }
+  if (!dist_scratch) return SSSP_ERR_ARG;
+  if ((rc = check_ws(ws, *ws_bytes, need))) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  sssp_opts sy;
+  sssp_opts_init(&sy);
+  sy.flags = SSSP_F_SYNC;
+  if ((rc = check_sync(sy, st))) return rc;
+  if (cache_path) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_json(cache_path);
+  }
+  // mean arc cost from a sample of the first graph's weights
+  double mean_w = graphs[0].wtype == SSSP_W_U32 ? 128.0 : 1.0;
+  if (graphs[0].m > 0) {
+    const int k = std::min(graphs[0].m, 1 << 16);
+    std::vector<uint32_t> h(k);
+    if (hipStreamSynchronize(st) != hipSuccess ||
+        hipMemcpy(h.data(), graphs[0].w, sizeof(uint32_t) * k, hipMemcpyDeviceToHost) !=
+            hipSuccess)
+      return SSSP_ERR_HIP;
+    double sum = 0;
+    for (uint32_t x : h) {
+      float f;
+      std::memcpy(&f, &x, 4);
+      sum += graphs[0].wtype == SSSP_W_U32 ? (double)x : (double)f;
+    }
+    mean_w = std::max(sum / k, graphs[0].wtype == SSSP_W_U32 ? 1.0 : 1e-30);
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return SSSP_ERR_HIP;
+  struct Cleanup {
+    hipEvent_t a, b;
+    ~Cleanup() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+      g_solve_time_limit_s = 30.0;
+    }
+  } cleanup{e0, e1};
+  sssp_opts cur;
+  sssp_opts_init(&cur);
+  cur.delta = fixed.delta;  // 0 = each graph's automatic width
+  cur.num_partitions = fixed.num_partitions;
+  cur.wg_size = fixed.wg_size ? fixed.wg_size : 512;
+  cur.num_workgroups = fixed.num_workgroups;
+  float best_ms = 1e30f;
+  bool found = false;
+  auto trial = [&](const sssp_opts &cand) -> int {
+    g_solve_time_limit_s = found ? std::min(30.0, std::max(0.02, 4e-3 * best_ms)) : 30.0;
+    sssp_opts o = cand;
+    o.flags = SSSP_F_NO_AUTOTUNE | SSSP_F_SYNC;
+    o.event_start = e0;
+    o.event_stop = e1;
+    float ms_min = 1e30f;
+    for (int rep = 0; rep < 2; rep++) {
+      size_t b = *ws_bytes;
+      const int r = sssp_solve_batch(num_graphs, graphs, num_solves, solve_graph, solve_source,
+                                     out_offset, &o, dist_scratch, nullptr, nullptr, nullptr,
+                                     ws, &b, stream);
+      if (r == SSSP_ERR_TIMEOUT && found) return SSSP_OK;
+      if (r != SSSP_OK) return r;
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return SSSP_ERR_HIP;
+      ms_min = std::min(ms_min, ms);
+    }
+    if (ms_min < best_ms) {
+      best_ms = ms_min;
+      cur = cand;
+      found = true;
+    }
+    return SSSP_OK;
+  };
+  if ((rc = trial(cur))) return rc;
+  if (fixed.delta == 0) {
+    const sssp_opts base = cur;
+    for (double f : {0.25, 0.5, 1.0, 2.0, 4.0}) {
+      sssp_opts c = base;
+      c.delta = mean_w * f;
+      if ((rc = trial(c))) return rc;
+    }
+  }
+  if (fixed.num_partitions == 0) {
+    const sssp_opts base = cur;
+    for (int p : parts) {
+      if (p == base.num_partitions) continue;
+      sssp_opts c = base;
+      c.num_partitions = p;
+      if ((rc = trial(c))) return rc;
+    }
+  }
+  if (fixed.wg_size == 0) {
+    sssp_opts c = cur;
+    c.wg_size = 256;
+    if ((rc = trial(c))) return rc;
+  }
+  if (fixed.num_workgroups == 0) {
+    const sssp_opts base = cur;
+    const int cus = device_info().cus;
+    for (int gw : {cus / 2, 2 * cus, 4 * cus}) {
+      sssp_opts c = base;
+      c.num_workgroups = gw;
+      if ((rc = trial(c))) return rc;
+    }
+  }
+  if (!found) return SSSP_ERR_TIMEOUT;
+  sssp_opts out = cur;
+  out.flags = 0;
+  out.event_start = nullptr;
+  out.event_stop = nullptr;
+  *best = out;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_cache[batch_key(num_graphs, graphs, num_solves)] = out;
     if (cache_path) save_json(cache_path);
   }
   return SSSP_OK;

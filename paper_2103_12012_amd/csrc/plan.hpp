@@ -34,7 +34,10 @@ float auto_delta_factor(int n, long long m);
 // sssp_autotune lowers it so that a slow candidate ends early.
 extern thread_local double g_solve_time_limit_s;
 
-// autotune.hip: cached best options for graphs of this signature, if any.
+// autotune.hip: cached best options for graphs of this signature, if any,
+// and for a batch of this signature.
 bool autotune_lookup(const sssp_csr &g, sssp_opts *out);
+bool autotune_lookup_batch(int num_graphs, const sssp_csr *graphs, int num_solves,
+                           sssp_opts *out);
 
 }  // namespace sssp_impl

@@ -17,7 +17,7 @@
 //  * the scan of an arc stops at its first witness.
 //
 // The scans advance in rounds: each live arc takes a chunk of its list
-// (16 entries, doubling every round), the chunks of all live arcs of a
+// (Q_D0 entries, doubling every round), the chunks of all live arcs of a
 // batch are laid end to end over the lanes, and finished arcs drop out.
 //
 //  * arcs with |N_out(u)| <= |N_in(x)| ("x-side") are grouped by x and use
@@ -94,7 +94,7 @@ struct TbArgs {
   int32_t *cnt;     // n*R: in-degree replicas
   int32_t *cptr;    // n*R+1: CSC offsets per replica (column x starts at cptr[x*R])
   int32_t *cb;      // n+1: column x is [cb[x], cb[x+1])
-  int32_t *cursor;  // n*R: scatter cursors
+  int32_t *rank;    // m: position of arc e among the arcs of its column replica
   int2 *cyw;        // m: CSC entries (tail, cost); sorted lists by cost
   int32_t *ceid;    // m: CSC -> CSR edge id (moves with cyw)
   int2 *rs;         // m: CSR rows as (head, cost); sorted lists by cost
@@ -183,10 +183,7 @@ __global__ void k_tb_zero(TbArgs a) {
   const int stride = gridDim.x * blockDim.x;
   for (int e = t; e < a.m; e += stride) a.keep[e] = 1;
   const long long nr = (long long)a.n * a.rep;
-  for (long long i = t; i < nr; i += stride) {
-    a.cnt[i] = 0;
-    a.cursor[i] = 0;
-  }
+  for (long long i = t; i < nr; i += stride) a.cnt[i] = 0;
   for (int i = t; i < 2 * a.n; i += stride) {
     a.work[i] = 0;
     a.hl[0].items[i] = 0;
@@ -207,19 +204,25 @@ __global__ void k_tb_tails(TbArgs a) {
 
 __device__ __forceinline__ int rep_of(const TbArgs &a, int e) { return e & (a.rep - 1); }
 
+// Thread per arc: count the in-degree replicas; the count before the arc is
+// its rank within its column replica.
 __global__ void k_tb_indeg(TbArgs a) {
   if (*a.status) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int stride = gridDim.x * blockDim.x;
   for (int e = t; e < a.m; e += stride) {
     const int x = a.col[e];
-    if ((unsigned)x < (unsigned)a.n) atomicAdd(&a.cnt[(long long)x * a.rep + rep_of(a, e)], 1);
-    else set_status(a.status, SSSP_ERR_CSR);
+    if ((unsigned)x < (unsigned)a.n) {
+      a.rank[e] = atomicAdd(&a.cnt[(long long)x * a.rep + rep_of(a, e)], 1);
+    } else {
+      a.rank[e] = 0;
+      set_status(a.status, SSSP_ERR_CSR);
+    }
   }
 }
 
-// Thread per arc: scatter into the CSC (each arc into its replica's range)
-// and copy the row entries.
+// Thread per arc: scatter into the CSC at its replica's offset plus its
+// rank (no atomics), and copy the row entries.
 __global__ void k_tb_fill(TbArgs a) {
   if (*a.status) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -229,7 +232,7 @@ __global__ void k_tb_fill(TbArgs a) {
     const int u = a.src[e];
     const uint32_t wv = a.w[e];
     const long long c = (long long)x * a.rep + rep_of(a, e);
-    const int pos = a.cptr[c] + atomicAdd(&a.cursor[c], 1);
+    const int pos = a.cptr[c] + a.rank[e];
     a.cyw[pos] = make_int2(u, (int)wv);
     a.ceid[pos] = e;
     a.rs[e] = make_int2(x, (int)wv);
@@ -950,7 +953,7 @@ __global__ void k_compact(const int32_t *row_ptr, const int32_t *col, const uint
 namespace {
 struct PruneLayout {
   int rep;
-  size_t src, cnt, cptr, cb, cursor, cyw, ceid, rs, sl, work, hflag, hl[2][6], gsz,
+  size_t src, cnt, cptr, cb, rank, cyw, ceid, rs, sl, work, hflag, hl[2][6], gsz,
       goff, gkey, gval, tmp, misc, pos, total;
 };
 
@@ -978,7 +981,7 @@ PruneLayout prune_layout(int n, int m, bool compact) {
   L.cnt = take(4 * nr);
   L.cptr = take(4 * (nr + 1));
   L.cb = take(4 * ((size_t)n + 1));
-  L.cursor = take(4 * nr);
+  L.rank = take(4ull * m);
   L.cyw = take(8ull * m);
   L.ceid = take(4ull * m);
   L.rs = take(8ull * m);
@@ -1044,7 +1047,7 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   a.cnt = reinterpret_cast<int32_t *>(ws + L.cnt);
   a.cptr = reinterpret_cast<int32_t *>(ws + L.cptr);
   a.cb = reinterpret_cast<int32_t *>(ws + L.cb);
-  a.cursor = reinterpret_cast<int32_t *>(ws + L.cursor);
+  a.rank = reinterpret_cast<int32_t *>(ws + L.rank);
   a.cyw = reinterpret_cast<int2 *>(ws + L.cyw);
   a.ceid = reinterpret_cast<int32_t *>(ws + L.ceid);
   a.rs = reinterpret_cast<int2 *>(ws + L.rs);

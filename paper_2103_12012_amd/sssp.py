@@ -90,8 +90,11 @@ def lib() -> ctypes.CDLL:
         L.sssp_backward.argtypes = [P(CSR), _i32, _vp, _vp, _vp, _vp, P(Opts), _vp, _vp, _sz,
                                     _vp]
         L.sssp_autotune.argtypes = [P(CSR), _i32, _vp, P(Opts), ctypes.c_char_p, _vp, _sz, _vp]
+        L.sssp_autotune_batch.argtypes = [_i32, P(CSR), _i32, P(_i32), P(_i32),
+                                          P(ctypes.c_int64), _vp, P(Opts), ctypes.c_char_p,
+                                          _vp, _sz, _vp]
         for f in ("sssp_prune", "sssp_solve", "sssp_solve_batch", "sssp_backward",
-                  "sssp_autotune"):
+                  "sssp_autotune", "sssp_autotune_batch"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -325,6 +328,28 @@ class BatchSolver:
                                     _ptr(self.ws), ctypes.byref(nb), _stream())
         _check(rc, "sssp_solve_batch")
         return self.dist, self.pred, self.pred_edge
+
+    def autotune(self, cache_path: str | None = None, **fixed) -> dict:
+        """Tune this batched launch (sssp_autotune_batch); later automatic
+        launches of batches with the same signature use the result.  The
+        workspace is sized again for the tuned options."""
+        L = lib()
+        best = make_opts(validate=False, **fixed)
+        args = (len(self._keep), self.gs, len(self.offsets), self.solve_graph, self.solve_source,
+                self.out_offset)
+        dev = self.dist.device
+        ws = _workspace(lambda nb: L.sssp_autotune_batch(*args, None, ctypes.byref(best), None,
+                                                         None, nb, None), dev)
+        nb = ctypes.c_size_t(ws.numel())
+        path = cache_path.encode() if cache_path else None
+        rc = L.sssp_autotune_batch(*args, _ptr(self.dist), ctypes.byref(best), path, _ptr(ws),
+                                   ctypes.byref(nb), _stream())
+        _check(rc, "sssp_autotune_batch")
+        del ws
+        self.ws = _workspace(lambda q: L.sssp_solve_batch(
+            *args, ctypes.byref(self.opts), None, None, None, None, None, q, None), dev)
+        return {"delta": best.delta, "num_partitions": best.num_partitions,
+                "wg_size": best.wg_size, "num_workgroups": best.num_workgroups}
 
     def split(self, t):
         """Per-solve views of a batched output tensor."""

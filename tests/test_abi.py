@@ -30,7 +30,8 @@ def ws_query(lib, g, source=0, opts=None):
 def test_exports_every_declared_symbol(lib):
     names = sssp.declared_symbols()
     assert set(names) >= {"sssp_prune", "sssp_solve", "sssp_solve_batch", "sssp_backward",
-                          "sssp_strerror", "sssp_autotune", "sssp_opts_init", "sssp_version"}
+                          "sssp_strerror", "sssp_autotune", "sssp_autotune_batch", "sssp_opts_init",
+                          "sssp_version"}
     for s in names:
         assert hasattr(lib, s), s
 
@@ -142,3 +143,20 @@ def test_batch_host_errors(lib):
     assert args(ss=(ctypes.c_int32 * 3)(0, 5, 20)) == -2
     gs[1].wtype = sssp.W_F32
     assert args() == -1
+
+
+def test_autotune_batch_host_errors(lib):
+    """Argument errors of sssp_autotune_batch are found on the host."""
+    g = sssp.CSR()
+    g.n, g.m, g.wtype = 4, 0, 0
+    nb = ctypes.c_size_t(0)
+    sg = (ctypes.c_int32 * 1)(0)
+    ss = (ctypes.c_int32 * 1)(0)
+    off = (ctypes.c_int64 * 1)(0)
+    o = sssp.make_opts(validate=False)
+    # no best options
+    assert lib.sssp_autotune_batch(1, ctypes.byref(g), 1, sg, ss, off, None, None, None, None,
+                                   ctypes.byref(nb), None) == -1
+    # no graphs
+    assert lib.sssp_autotune_batch(0, ctypes.byref(g), 1, sg, ss, off, None, ctypes.byref(o),
+                                   None, None, ctypes.byref(nb), None) == -1

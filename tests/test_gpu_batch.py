@@ -79,3 +79,19 @@ def test_batch_hip_graph_replays():
         torch.cuda.synchronize()
         assert torch.equal(b.dist, eager)
         check(graphs, sg, ss, (b.split(b.dist), b.split(b.pred), b.split(b.pred_edge)))
+
+
+def test_batch_autotune_then_parity(tmp_path):
+    """sssp_autotune_batch: valid options, a cache entry under the batch
+    signature, and the tuned (automatic) launch keeps bit-exact parity."""
+    graphs, sg, ss = make_batch(4, 8, 10, seed=5)
+    S = sssp_mod()
+    dg = [dev(g) for g in graphs]
+    b = S.BatchSolver(dg, sg, ss)
+    path = tmp_path / "batch.json"
+    best = b.autotune(cache_path=str(path))
+    assert best["wg_size"] in (256, 512) and best["num_partitions"] >= 0
+    assert "|batch|" in path.read_text()
+    b()
+    torch.cuda.synchronize()
+    check(graphs, sg, ss, (b.split(b.dist), b.split(b.pred), b.split(b.pred_edge)))
