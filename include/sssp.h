@@ -107,7 +107,8 @@ typedef struct {
   int32_t lag;             /* sssp_solve: a partition may expand its lowest
                               bucket only while its pending minimum is within
                               lag * delta of the least pending distance of the
-                              whole graph; 0 = auto, < 0 = unbounded (fully
+                              whole graph; 0 = auto (the autotune cache,
+                              else 1), < 0 = unbounded (fully
                               asynchronous partitions).  Batched solves are
                               always unbounded.  Results never depend on it. */
   void *event_start;       /* optional hipEvent_t recorded right before the

@@ -187,7 +187,7 @@ SolveLayout solve_layout(int nsolves, const std::vector<int> &ns, int nunits) {
   L.desc = take(sizeof(SolveDesc) * (size_t)nsolves);
   L.unit_solve = take(sizeof(int32_t) * (size_t)nunits);
   L.unit_min = take(sizeof(unsigned long long) * (size_t)nunits);
-  L.abits = take(sizeof(uint32_t) * (size_t)nabw);
+  L.abits = take(sizeof(uint32_t) * ABW_STRIDE * (size_t)nabw);
   L.label.resize(nsolves);
   L.dirty.resize(nsolves);
   for (int i = 0; i < nsolves; i++) {
@@ -238,7 +238,7 @@ int run_solves(std::vector<SolveDesc> &descs, const SolveLayout &L, int nunits, 
   a.window = DELTA_INF;
   a.auto_lag = 0;
   if (descs.size() == 1 && o.lag >= 0 && descs[0].delta != DELTA_INF) {
-    const unsigned long long lag = o.lag > 0 ? (unsigned long long)o.lag : 2ull;
+    const unsigned long long lag = o.lag > 0 ? (unsigned long long)o.lag : 1ull;
     if (descs[0].delta == DELTA_AUTO) a.auto_lag = (int)lag;
     else a.window = window_units(descs[0].delta, lag, wtype);
   }

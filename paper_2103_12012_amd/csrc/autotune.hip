@@ -220,7 +220,7 @@ extern "C" int sssp_autotune(const sssp_csr *g, int32_t source, void *dist_scrat
   cur.num_partitions = fixed.num_partitions > 0 ? fixed.num_partitions
                                                 : default_parts(g->n, g->m);
   cur.wg_size = fixed.wg_size ? fixed.wg_size : 512;
-  cur.lag = fixed.lag ? fixed.lag : 2;
+  cur.lag = fixed.lag ? fixed.lag : 1;
   cur.num_workgroups = fixed.num_workgroups;
   float best_ms = 1e30f;
   bool found = false;
@@ -272,7 +272,7 @@ extern "C" int sssp_autotune(const sssp_csr *g, int32_t source, void *dist_scrat
   }
   if (fixed.lag == 0 && cur.delta > 0) {
     const sssp_opts base = cur;
-    for (int l : {1, 4, -1}) {
+    for (int l : {2, 4, -1}) {
       sssp_opts c = base;
       c.lag = l;
       if ((rc = trial(c))) return rc;

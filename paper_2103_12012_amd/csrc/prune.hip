@@ -26,8 +26,11 @@
 //  * N_in(x) comes from a CSC (in-lists) built here by a counting sort;
 //  * a table owner with a short list and little work is handled by one
 //    wavefront with a private LDS table; heavier owners are split into
-//    workgroup items of about HV_TARGET probes over an LDS table, or over an
-//    L2-resident global table when the list exceeds HV_TCAP entries.
+//    workgroup items of about HV_TARGET estimated probes, in three tiers by
+//    list length (LDS tables of 1024 and 4096 slots for 256-thread
+//    workgroups, 16384 slots for 1024-thread workgroups, or an L2-resident
+//    global table when the list exceeds HV_TCAP entries), so that short
+//    tables leave room for more resident workgroups.
 //
 // Integer costs are summed in 64 bits; fp32 costs are summed in double,
 // which decides w1 + w2 < W exactly for fp32 operands (the sum is exact
@@ -44,7 +47,8 @@ constexpr int LT_DEG = 128;          // light owner: list length
 constexpr int LT_SLOTS = 256;        // light owner: wave-private hash slots
 constexpr int LT_WORK = 8192;        // light owner: probes
 constexpr int LT_BS = 256;
-constexpr int LT_CHUNK = 16;         // light owners dealt to a wave at a time
+constexpr int HS_TCAP = 512;         // small heavy owner: longest list
+constexpr int HS_SLOTS = 1024;
 constexpr int HM_TCAP = 2048;        // medium heavy owner: longest list
 constexpr int HM_SLOTS = 4096;
 constexpr int HM_BS = 256;
@@ -102,13 +106,14 @@ struct TbArgs {
                     //     ones (> SORT_WAVE entries) from the back
   int32_t *work;    // 2n: probes of owner i (i < n: in-table of i; else out-table of i-n)
   int32_t *hflag;   // 2n: 0 light, 1 medium, 2 big heavy owner
-  HList hl[2];      // heavy owners: [0] medium, [1] big
+  HList hl[3];      // heavy owners: [0] small, [1] medium, [2] big
   int32_t *gsz;     // 2n: global table size in units of G_UNIT slots (0 = LDS)
   int32_t *goff;    // 2n+1: exclusive scan of gsz
   int32_t *gkey;    // global tables: keys (-1 = empty)
   uint32_t *gval;   //                cheapest parallel arc
-  int32_t *tickets; // [0] / [1] medium / big heavy items, [2] short and
-                    // [3] long lists to sort
+  int32_t *llist;   // 2n: light owners (order of appending)
+  int32_t *tickets; // [0..2] heavy items per tier, [3] short and [4] long
+                    // lists to sort, [5] light owners
   int32_t *status;
   sssp_stats *stats;
 };
@@ -158,10 +163,7 @@ __device__ __forceinline__ void wave_sync() {
 __global__ void k_tb_status(TbArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *a.status = 0;
-    a.tickets[0] = 0;
-    a.tickets[1] = 0;
-    a.tickets[2] = 0;
-    a.tickets[3] = 0;
+    for (int k = 0; k < 6; k++) a.tickets[k] = 0;
   }
   if (a.stats && blockIdx.x == 0 && threadIdx.x < (int)(sizeof(sssp_stats) / 4))
     reinterpret_cast<uint32_t *>(a.stats)[threadIdx.x] = 0u;
@@ -186,8 +188,7 @@ __global__ void k_tb_zero(TbArgs a) {
   for (long long i = t; i < nr; i += stride) a.cnt[i] = 0;
   for (int i = t; i < 2 * a.n; i += stride) {
     a.work[i] = 0;
-    a.hl[0].items[i] = 0;
-    a.hl[1].items[i] = 0;
+    for (int k = 0; k < 3; k++) a.hl[k].items[i] = 0;
   }
 }
 
@@ -306,7 +307,7 @@ __global__ __launch_bounds__(CLS_BS) void k_tb_sort_class(TbArgs a) {
     if (threadIdx.x < 2) {
       int tot = 0;
       for (int w = 0; w < CLS_BS / WAVE; w++) tot += s_cnt[threadIdx.x][w];
-      s_base[threadIdx.x] = tot ? atomicAdd(&a.tickets[2 + threadIdx.x], tot) : 0;
+      s_base[threadIdx.x] = tot ? atomicAdd(&a.tickets[3 + threadIdx.x], tot) : 0;
     }
     __syncthreads();
     int offs = s_base[0], offl = s_base[1];
@@ -393,7 +394,7 @@ __global__ void k_tb_sort_small(TbArgs a) {
   if (*a.status) return;
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int nwaves = gridDim.x * blockDim.x / WAVE;
-  const int ns = a.tickets[2];
+  const int ns = a.tickets[3];
   for (int j = wave; j < ns; j += nwaves) {
     const SortSeg g = sort_seg(a, a.sl[j]);
     if (g.len <= WAVE) wave_sort_list<1>(a, g);
@@ -411,7 +412,7 @@ __global__ __launch_bounds__(SORT_BS) void k_tb_sort_mid(TbArgs a) {
   __shared__ int sp[SORT_MAX];
   if (*a.status) return;
   const int tid = threadIdx.x;
-  const int nl = a.tickets[3];
+  const int nl = a.tickets[4];
   for (int j = blockIdx.x; j < nl; j += gridDim.x) {
     const SortSeg g = sort_seg(a, a.sl[2 * a.n - 1 - j]);
     int N = 2 * SORT_WAVE;
@@ -503,18 +504,31 @@ __device__ __forceinline__ int owner_len(const TbArgs &a, int i) {
   return a.row_ptr[u + 1] - a.row_ptr[u];
 }
 
+// Tier of every owner; light owners with work are appended to llist (one
+// atomic per wave).
 __global__ void k_tb_classify(TbArgs a) {
   if (*a.status) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int stride = gridDim.x * blockDim.x;
-  for (int i = t; i < 2 * a.n; i += stride) {
-    const int wk = a.work[i];
-    const int len = owner_len(a, i);
+  const int lim = (2 * a.n + WAVE - 1) / WAVE * WAVE;  // whole waves stay in the loop
+  for (int i = t; i < lim; i += stride) {
+    const bool in = i < 2 * a.n;
+    const int wk = in ? a.work[i] : 0;
+    const int len = in ? owner_len(a, i) : 0;
     const bool heavy = wk > 0 && (len > LT_DEG || wk > LT_WORK);
-    const bool big = heavy && len > HM_TCAP;
-    a.hflag[i] = heavy ? (big ? 2 : 1) : 0;
-    a.hl[0].flag[i] = heavy && !big;
-    a.hl[1].flag[i] = big;
+    const bool light = wk > 0 && !heavy;
+    const unsigned long long bl = __ballot(light);
+    int base = 0;
+    if (lane_id() == 0 && bl) base = atomicAdd(&a.tickets[5], __popcll(bl));
+    base = __shfl(base, 0, WAVE);
+    if (light) a.llist[base + __popcll(bl & ((1ull << lane_id()) - 1ull))] = i;
+    if (!in) continue;
+    const int tier = !heavy ? 0 : (len > HM_TCAP ? 3 : (len > HS_TCAP ? 2 : 1));
+    a.hflag[i] = tier;
+    a.hl[0].flag[i] = tier == 1;
+    a.hl[1].flag[i] = tier == 2;
+    a.hl[2].flag[i] = tier == 3;
+    const bool big = tier == 3;
     int g = 0;
     if (big && len > HV_TCAP) g = (1 << tb_bits(len, 6)) / G_UNIT;
     a.gsz[i] = g;
@@ -543,7 +557,7 @@ __global__ void k_tb_item_map(TbArgs a) {
   if (*a.status) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int stride = gridDim.x * blockDim.x;
-  for (int tier = 0; tier < 2; tier++) {
+  for (int tier = 0; tier < 3; tier++) {
     const HList &h = a.hl[tier];
     const int nh = h.pos[2 * a.n];
     for (int j = t; j < nh; j += stride) {
@@ -557,7 +571,7 @@ __global__ void k_tb_item_map(TbArgs a) {
 // insert the list (owners are taken in turn from the heavy list).
 __global__ __launch_bounds__(256) void k_tb_gtab(TbArgs a) {
   if (*a.status) return;
-  const HList &h = a.hl[1];
+  const HList &h = a.hl[2];
   const int nh = h.pos[2 * a.n];
   for (int j = blockIdx.x; j < nh; j += gridDim.x) {
     const int i = h.id[j];
@@ -793,7 +807,7 @@ __global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
     const int32_t *tkey;
     const uint32_t *tval;
     int tbits;
-    if (TIER == 1 && a.gsz[i]) {
+    if (TIER == 2 && a.gsz[i]) {
       const long long base = (long long)a.goff[i] * G_UNIT;
       tkey = a.gkey + base;
       tval = a.gval + base;
@@ -851,8 +865,7 @@ __global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
   if (a.stats && tid == 0 && probes) stat_add(&a.stats->wedges, probes);
 }
 
-// Light owners: one wave per owner, a private LDS table; owners are dealt
-// to the waves in fixed chunks.
+// Light owners: one wave per owner of llist, a private LDS table.
 template <int WT>
 __global__ __launch_bounds__(LT_BS) void k_tb_light(TbArgs a) {
   __shared__ TbLight sw[LT_BS / WAVE];
@@ -862,10 +875,10 @@ __global__ __launch_bounds__(LT_BS) void k_tb_light(TbArgs a) {
   const int gw = (blockIdx.x * LT_BS + threadIdx.x) / WAVE;
   const int nw = gridDim.x * (LT_BS / WAVE);
   unsigned long long probes = 0;
-  for (int i0 = gw * LT_CHUNK; i0 < 2 * a.n; i0 += nw * LT_CHUNK) {
-    const int i1 = min(2 * a.n, i0 + LT_CHUNK);
-    for (int i = i0; i < i1; i++) {
-      if (a.hflag[i] || a.work[i] == 0) continue;
+  const int nlight = a.tickets[5];
+  for (int j = gw; j < nlight; j += nw) {
+    {
+      const int i = a.llist[j];
       const Owner o = make_owner(a, i);
       const int tbits = tb_bits(o.llen, 5);
       const int tmask = (1 << tbits) - 1;
@@ -953,7 +966,7 @@ __global__ void k_compact(const int32_t *row_ptr, const int32_t *col, const uint
 namespace {
 struct PruneLayout {
   int rep;
-  size_t src, cnt, cptr, cb, rank, cyw, ceid, rs, sl, work, hflag, hl[2][6], gsz,
+  size_t src, cnt, cptr, cb, rank, cyw, ceid, rs, sl, llist, work, hflag, hl[3][6], gsz,
       goff, gkey, gval, tmp, misc, pos, total;
 };
 
@@ -986,9 +999,10 @@ PruneLayout prune_layout(int n, int m, bool compact) {
   L.ceid = take(4ull * m);
   L.rs = take(8ull * m);
   L.sl = take(4 * n2);
+  L.llist = take(4 * n2);
   L.work = take(4 * n2);
   L.hflag = take(4 * n2);
-  for (int t = 0; t < 2; t++) {
+  for (int t = 0; t < 3; t++) {
     L.hl[t][0] = take(4 * n2);                           // flag
     L.hl[t][1] = take(4 * (n2 + 1));                     // pos
     L.hl[t][2] = take(4 * n2);                           // id
@@ -1021,8 +1035,9 @@ void launch_resident(K kernel, int bs, int grid_cus, const TbArgs &a, hipStream_
 template <int WT>
 void launch_scan_kernels(const TbArgs &a, int grid_cus, hipStream_t st) {
   launch_resident(k_tb_light<WT>, LT_BS, grid_cus, a, st);
-  launch_resident(k_tb_heavy<WT, 0, HM_BS, HM_SLOTS, HM_Q>, HM_BS, grid_cus, a, st);
-  launch_resident(k_tb_heavy<WT, 1, TB_BS, HV_SLOTS, HV_Q>, TB_BS, grid_cus, a, st);
+  launch_resident(k_tb_heavy<WT, 0, HM_BS, HS_SLOTS, HM_Q>, HM_BS, grid_cus, a, st);
+  launch_resident(k_tb_heavy<WT, 1, HM_BS, HM_SLOTS, HM_Q>, HM_BS, grid_cus, a, st);
+  launch_resident(k_tb_heavy<WT, 2, TB_BS, HV_SLOTS, HV_Q>, TB_BS, grid_cus, a, st);
 }
 
 size_t prune_ws_bytes(int n, int m, bool compact) { return prune_layout(n, m, compact).total; }
@@ -1052,9 +1067,10 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   a.ceid = reinterpret_cast<int32_t *>(ws + L.ceid);
   a.rs = reinterpret_cast<int2 *>(ws + L.rs);
   a.sl = reinterpret_cast<int32_t *>(ws + L.sl);
+  a.llist = reinterpret_cast<int32_t *>(ws + L.llist);
   a.work = reinterpret_cast<int32_t *>(ws + L.work);
   a.hflag = reinterpret_cast<int32_t *>(ws + L.hflag);
-  for (int t = 0; t < 2; t++) {
+  for (int t = 0; t < 3; t++) {
     HList &h = a.hl[t];
     h.flag = reinterpret_cast<int32_t *>(ws + L.hl[t][0]);
     h.pos = reinterpret_cast<int32_t *>(ws + L.hl[t][1]);
@@ -1070,7 +1086,7 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   int32_t *tmp = reinterpret_cast<int32_t *>(ws + L.tmp);
   char *misc = ws + L.misc;
   a.tickets = reinterpret_cast<int32_t *>(misc);
-  a.status = reinterpret_cast<int32_t *>(misc + 16);
+  a.status = reinterpret_cast<int32_t *>(misc + 128);  // after 32 ticket counters
   a.stats = stats;
   int32_t *pos = out_row_ptr ? reinterpret_cast<int32_t *>(ws + L.pos) : nullptr;
   *status_out = a.status;
@@ -1089,12 +1105,12 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   hipLaunchKernelGGL(k_tb_sort_mid, dim3(grid_cus * 8), dim3(SORT_BS), 0, st, a);
   hipLaunchKernelGGL(k_tb_work, dim3(blocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_tb_classify, dim3(blocks), dim3(256), 0, st, a);
-  for (int t = 0; t < 2; t++)
+  for (int t = 0; t < 3; t++)
     if (launch_excl_scan(a.hl[t].flag, 2 * n, a.hl[t].pos, tmp, st) != hipSuccess)
       return SSSP_ERR_HIP;
   if (launch_excl_scan(a.gsz, 2 * n, a.goff, tmp, st) != hipSuccess) return SSSP_ERR_HIP;
   hipLaunchKernelGGL(k_tb_heavy_list, dim3(blocks), dim3(256), 0, st, a);
-  for (int t = 0; t < 2; t++)
+  for (int t = 0; t < 3; t++)
     if (launch_excl_scan(a.hl[t].items, 2 * n, a.hl[t].off, tmp, st) != hipSuccess)
       return SSSP_ERR_HIP;
   hipLaunchKernelGGL(k_tb_item_map, dim3(blocks), dim3(256), 0, st, a);

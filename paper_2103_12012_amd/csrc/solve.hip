@@ -90,6 +90,12 @@ template <> struct Dist<SSSP_W_F32> {
 };
 
 // ------------------------------------------------------------------ setup
+// Word of the active-unit bitmap holding unit u: each 32-unit word sits on a
+// 128-byte line of its own (ABW_STRIDE words apart), since every push that
+// activates a unit and every claim is an atomic on that word, and one shared
+// line serialises them all.
+__device__ __forceinline__ int abw(int u) { return (u >> 5) * ABW_STRIDE; }
+
 
 // Writes descriptors carried in the kernel arguments into the workspace, so
 // a captured launch replays without the host-side tables.
@@ -102,7 +108,7 @@ __global__ void k_write_desc(DescChunk c, SolveDesc *table) {
 __global__ void k_init_global(SolveArgs a, int nsolves) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int stride = gridDim.x * blockDim.x;
-  for (int i = t; i < a.nabw; i += stride) a.abits[i] = 0u;
+  for (int i = t; i < a.nabw; i += stride) a.abits[i * ABW_STRIDE] = 0u;
   if (t == 0) {
     a.ctrl->work = nsolves;  // every source starts pending
     a.ctrl->done = 0u;
@@ -135,7 +141,7 @@ __global__ void k_init(SolveArgs a) {
   }
   if (t == 0) {
     const int u = d.unit0 + ps;
-    aor(&a.abits[u >> 5], 1u << (u & 31));
+    aor(&a.abits[abw(u)], 1u << (u & 31));
   }
 }
 
@@ -276,7 +282,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
 #pragma unroll
         for (int j = 0; j < 4; j++) {
           const int u = u0 + j * BS + tid;
-          wv[j] = u < a.nunits ? ld_rlx(&abits[u >> 5]) : 0u;
+          wv[j] = u < a.nunits ? ld_rlx(&abits[abw(u)]) : 0u;
         }
 #pragma unroll
         for (int j = 0; j < 4; j++) {
@@ -311,7 +317,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
             act = (act0 >> j) & 1u;
             d = um0[j];
           } else {
-            act = u < a.nunits && ((ld_rlx(&abits[u >> 5]) >> (u & 31)) & 1u);
+            act = u < a.nunits && ((ld_rlx(&abits[abw(u)]) >> (u & 31)) & 1u);
             d = act ? ld_rlx(&unit_min[u]) : ~0ull;
           }
           if (act && (d == ~0ull || gmin == ~0ull || window == DELTA_INF ||
@@ -342,7 +348,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
           tried |= 1u << bi;
           const int u = (int)unit_unmix((uint32_t)bk, mixkey);
           const uint32_t mb = 1u << (u & 31);
-          if (aand_acq(&abits[u >> 5], ~mb) & mb) {
+          if (aand_acq(&abits[abw(u)], ~mb) & mb) {
             s_unit = u;
             s_gmin = gmin;
             break;
@@ -675,7 +681,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
           if (q != part) {
             const int gu = unit0 + q;
             amin(&unit_min[gu], (unsigned long long)nd[j]);
-            aor(&abits[gu >> 5], 1u << (gu & 31));
+            aor(&abits[abw(gu)], 1u << (gu & 31));
           } else {
             pmin = nd[j] < pmin ? nd[j] : pmin;
           }
@@ -741,7 +747,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
         if (!trunc && (window == DELTA_INF || Dist<WT>::within(rem, s_gmin, window)))
           s_stay = unit;
         else
-          aor(&abits[unit >> 5], 1u << (unit & 31));
+          aor(&abits[abw(unit)], 1u << (unit & 31));
       }
       st_tot += (unsigned long long)s_tot;
       st_upd += s_upd;
