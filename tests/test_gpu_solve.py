@@ -202,3 +202,43 @@ def test_auto_delta_fp32():
     width = np.float32(0.5 * g.w[idx].astype(np.float64).mean())
     assert abs(np.uint32(st["delta_bits"]).view(np.float32) - width) <= 1e-6 * width
     assert_solve_parity(g, s, (dist.cpu().numpy(), pred.cpu().numpy(), pe.cpu().numpy()))
+
+
+@pytest.mark.parametrize("delta", [-1.0, 1.0])
+def test_long_path_in_one_partition(delta):
+    """A 3000-vertex directed path inside one partition: one frontier vertex
+    per round, so a batch reaches its round cap and hands its queue back to
+    the inbox; the result must still be exact."""
+    n = 3000
+    u = np.arange(n - 1)
+    w = np.random.default_rng(3).integers(1, 9, size=n - 1).astype(np.uint32)
+    g = gen.from_arcs(n, u, u + 1, w)
+    assert_solve_parity(g, 0, gpu_solve(g, 0, num_partitions=1, delta=delta, lag=-1))
+
+
+def test_hub_floods_frontier_capacity():
+    """A hub with 40000 out-arcs inside one 32768-vertex partition fills far
+    more than one LDS frontier of inbox entries at once (the truncated
+    gather path), plus a second layer of arcs among the leaves."""
+    n = 40001
+    rng = np.random.default_rng(5)
+    u = np.concatenate([np.zeros(n - 1, np.int64), rng.integers(1, n, size=60000)])
+    v = np.concatenate([np.arange(1, n), rng.integers(1, n, size=60000)])
+    w = rng.integers(1, 50, size=u.size).astype(np.uint32)
+    keep = u != v
+    g = gen.from_arcs(n, u[keep], v[keep], w[keep])
+    for P in (2, 64):
+        assert_solve_parity(g, 0, gpu_solve(g, 0, num_partitions=P, delta=1000.0))
+
+
+def test_largest_partition_block():
+    """P = 1 on a graph of 70000 vertices is raised so that no block exceeds
+    32768 vertices (the LDS dedupe bitmap); the result is exact."""
+    g = gen.uniform(70000, 300000, seed=8)
+    S = sssp_mod()
+    rp, c, w = dev(g)
+    solver = S.Solver(rp, c, w, num_partitions=1, stats=True)
+    dist, pred, pe = solver(0, sync=True)
+    assert solver.stats.read()["num_partitions"] == 3
+    assert_solve_parity(g, 0, (dist.cpu().numpy().view(np.uint32), pred.cpu().numpy(),
+                               pe.cpu().numpy()))
