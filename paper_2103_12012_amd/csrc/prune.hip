@@ -423,7 +423,30 @@ __global__ __launch_bounds__(SORT_BS) void k_tb_sort_mid(TbArgs a) {
       sp[p] = pay;
     }
     __syncthreads();
-    for (int size = 2; size <= N; size <<= 1)
+    // the stages up to size SORT_WAVE in registers: each wave sorts whole
+    // SORT_WAVE-key chunks and stores them ascending or descending, as the
+    // network would leave them
+    for (int c = tid / WAVE; c < N / SORT_WAVE; c += SORT_BS / WAVE) {
+      unsigned long long k[SORT_WAVE / WAVE];
+      int pv[SORT_WAVE / WAVE];
+      const int lane = lane_id();
+#pragma unroll
+      for (int r = 0; r < SORT_WAVE / WAVE; r++) {
+        k[r] = sk[c * SORT_WAVE + lane + WAVE * r];
+        pv[r] = sp[c * SORT_WAVE + lane + WAVE * r];
+      }
+      wave_sort<SORT_WAVE / WAVE>(k, pv);
+      const bool asc = ((c * SORT_WAVE) & SORT_WAVE) == 0;
+#pragma unroll
+      for (int r = 0; r < SORT_WAVE / WAVE; r++) {
+        const int e = lane + WAVE * r;
+        const int dst = c * SORT_WAVE + (asc ? e : SORT_WAVE - 1 - e);
+        sk[dst] = k[r];
+        sp[dst] = pv[r];
+      }
+    }
+    __syncthreads();
+    for (int size = 2 * SORT_WAVE; size <= N; size <<= 1)
       for (int jj = size >> 1; jj > 0; jj >>= 1) {
         for (int i = tid; i < N / 2; i += SORT_BS) {
           const int lo = 2 * i - (i & (jj - 1));
@@ -505,33 +528,45 @@ __device__ __forceinline__ int owner_len(const TbArgs &a, int i) {
 }
 
 // Tier of every owner; light owners with work are appended to llist (one
-// atomic per wave).
-__global__ void k_tb_classify(TbArgs a) {
+// atomic per workgroup pass).
+constexpr int CLF_BS = 1024;
+__global__ __launch_bounds__(CLF_BS) void k_tb_classify(TbArgs a) {
+  __shared__ int s_cnt[CLF_BS / WAVE];
+  __shared__ int s_base;
   if (*a.status) return;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int stride = gridDim.x * blockDim.x;
-  const int lim = (2 * a.n + WAVE - 1) / WAVE * WAVE;  // whole waves stay in the loop
-  for (int i = t; i < lim; i += stride) {
-    const bool in = i < 2 * a.n;
+  const int lane = lane_id();
+  const int wid = threadIdx.x / WAVE;
+  const int n2 = 2 * a.n;
+  for (int i0 = blockIdx.x * CLF_BS; i0 < n2; i0 += gridDim.x * CLF_BS) {
+    const int i = i0 + threadIdx.x;
+    const bool in = i < n2;
     const int wk = in ? a.work[i] : 0;
     const int len = in ? owner_len(a, i) : 0;
     const bool heavy = wk > 0 && (len > LT_DEG || wk > LT_WORK);
     const bool light = wk > 0 && !heavy;
     const unsigned long long bl = __ballot(light);
-    int base = 0;
-    if (lane_id() == 0 && bl) base = atomicAdd(&a.tickets[5], __popcll(bl));
-    base = __shfl(base, 0, WAVE);
-    if (light) a.llist[base + __popcll(bl & ((1ull << lane_id()) - 1ull))] = i;
-    if (!in) continue;
-    const int tier = !heavy ? 0 : (len > HM_TCAP ? 3 : (len > HS_TCAP ? 2 : 1));
-    a.hflag[i] = tier;
-    a.hl[0].flag[i] = tier == 1;
-    a.hl[1].flag[i] = tier == 2;
-    a.hl[2].flag[i] = tier == 3;
-    const bool big = tier == 3;
-    int g = 0;
-    if (big && len > HV_TCAP) g = (1 << tb_bits(len, 6)) / G_UNIT;
-    a.gsz[i] = g;
+    if (lane == 0) s_cnt[wid] = __popcll(bl);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int w = 0; w < CLF_BS / WAVE; w++) tot += s_cnt[w];
+      s_base = tot ? atomicAdd(&a.tickets[5], tot) : 0;
+    }
+    __syncthreads();
+    int off = s_base;
+    for (int w = 0; w < wid; w++) off += s_cnt[w];
+    if (light) a.llist[off + __popcll(bl & ((1ull << lane) - 1ull))] = i;
+    if (in) {
+      const int tier = !heavy ? 0 : (len > HM_TCAP ? 3 : (len > HS_TCAP ? 2 : 1));
+      a.hflag[i] = tier;
+      a.hl[0].flag[i] = tier == 1;
+      a.hl[1].flag[i] = tier == 2;
+      a.hl[2].flag[i] = tier == 3;
+      int g = 0;
+      if (tier == 3 && len > HV_TCAP) g = (1 << tb_bits(len, 6)) / G_UNIT;
+      a.gsz[i] = g;
+    }
+    __syncthreads();
   }
 }
 
@@ -567,8 +602,20 @@ __global__ void k_tb_item_map(TbArgs a) {
   }
 }
 
-// One workgroup per heavy owner with a long list: clear its global table and
-// insert the list (owners are taken in turn from the heavy list).
+// Global tables of the longest lists: every slot cleared (grid stride over
+// all tables), then the lists inserted with blockIdx.x over the owners and
+// blockIdx.y over slices of each list.
+__global__ void k_tb_gclear(TbArgs a) {
+  if (*a.status) return;
+  const long long total = (long long)a.goff[2 * a.n] * G_UNIT;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long s = t; s < total; s += stride) {
+    a.gkey[s] = -1;
+    a.gval[s] = VAL_INF;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_tb_gtab(TbArgs a) {
   if (*a.status) return;
   const HList &h = a.hl[2];
@@ -579,25 +626,15 @@ __global__ __launch_bounds__(256) void k_tb_gtab(TbArgs a) {
     if (!g) continue;
     const long long base = (long long)a.goff[i] * G_UNIT;
     const int slots = g * G_UNIT;
-    int32_t *key = a.gkey + base;
-    uint32_t *val = a.gval + base;
-    for (int s = threadIdx.x; s < slots; s += blockDim.x) {
-      key[s] = -1;
-      val[s] = VAL_INF;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const int bits = tb_bits(slots / 2, 6);
     const bool out_list = i >= a.n;
     const int t = out_list ? i - a.n : i;
     const int lb = out_list ? a.row_ptr[t] : cbeg(a, t);
     const int ll = out_list ? a.row_ptr[t + 1] - lb : clen(a, t);
-    for (int p = threadIdx.x; p < ll; p += blockDim.x) {
+    for (int p = blockIdx.y * blockDim.x + threadIdx.x; p < ll; p += gridDim.y * blockDim.x) {
       const int2 yw = out_list ? a.rs[lb + p] : a.cyw[lb + p];
-      if (yw.x != t) tb_insert(key, val, slots - 1, bits, yw.x, (uint32_t)yw.y);
+      if (yw.x != t) tb_insert(a.gkey + base, a.gval + base, slots - 1, bits, yw.x, (uint32_t)yw.y);
     }
-    __syncthreads();
   }
 }
 
@@ -1104,7 +1141,7 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   hipLaunchKernelGGL(k_tb_sort_small, dim3(blocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_tb_sort_mid, dim3(grid_cus * 8), dim3(SORT_BS), 0, st, a);
   hipLaunchKernelGGL(k_tb_work, dim3(blocks), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(k_tb_classify, dim3(blocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_tb_classify, dim3(grid_cus * 2), dim3(CLF_BS), 0, st, a);
   for (int t = 0; t < 3; t++)
     if (launch_excl_scan(a.hl[t].flag, 2 * n, a.hl[t].pos, tmp, st) != hipSuccess)
       return SSSP_ERR_HIP;
@@ -1114,7 +1151,8 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
     if (launch_excl_scan(a.hl[t].items, 2 * n, a.hl[t].off, tmp, st) != hipSuccess)
       return SSSP_ERR_HIP;
   hipLaunchKernelGGL(k_tb_item_map, dim3(blocks), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(k_tb_gtab, dim3(grid_cus * 4), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_tb_gclear, dim3(blocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_tb_gtab, dim3(grid_cus, 16), dim3(256), 0, st, a);
   if (ev_start && hipEventRecord((hipEvent_t)ev_start, st) != hipSuccess) return SSSP_ERR_HIP;
   if (g.wtype == SSSP_W_U32) launch_scan_kernels<SSSP_W_U32>(a, grid_cus, st);
   else launch_scan_kernels<SSSP_W_F32>(a, grid_cus, st);
