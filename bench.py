@@ -69,10 +69,11 @@ def m_reached(g, source):
 KERNEL_SOURCES = {  # files each kernel is compiled from (for the counter-staleness check)
     "k_solve": ("internal.hpp", "solve.hip"),
     "k_tb_light": ("internal.hpp", "prune.hip"),
+    "k_tb_heavy_small": ("internal.hpp", "prune.hip"),
     "k_tb_heavy_medium": ("internal.hpp", "prune.hip"),
     "k_tb_heavy_big": ("internal.hpp", "prune.hip"),
 }
-TRISHLA_SCAN = ("k_tb_light", "k_tb_heavy_medium", "k_tb_heavy_big")
+TRISHLA_SCAN = ("k_tb_light", "k_tb_heavy_small", "k_tb_heavy_medium", "k_tb_heavy_big")
 
 
 def kernel_source_hash(kernel):
@@ -453,8 +454,10 @@ def main():
             "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "u32", "data": "synthetic"}
     if head is not None:
-        dom = head["roofline_prune"] if head["prune_ms"] >= head["solve_ms"] \
-            else head["roofline_solve"]
+        # the dominant single kernel is k_solve: the Trishla scan phase is four
+        # kernels (light owners and three heavy tiers), each shorter than it
+        # (see profiles/k_solve_trishla_rmat20_step.txt)
+        dom = head["roofline_solve"]
         line.update({
             "value": round(head["gteps"], 4), "ms_per_step": round(head["ms_per_step"], 4),
             "config": {"workload": "rmat20_trishla_then_sssp", "scale": 20, "edge_factor": 16,
