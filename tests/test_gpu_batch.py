@@ -95,3 +95,34 @@ def test_batch_autotune_then_parity(tmp_path):
     b()
     torch.cuda.synchronize()
     check(graphs, sg, ss, (b.split(b.dist), b.split(b.pred), b.split(b.pred_edge)))
+
+
+def test_c4_full_size_batched_launch():
+    """The batched workload at full size, as the benchmark runs it: 64 R-MAT
+    graphs of scales 12..18 (seed 4, graph i seed 4000+i), 4 random sources
+    each, tuned as a whole and launched once through a captured HIP graph;
+    every one of the 256 results equals the single-source oracle."""
+    rng = np.random.default_rng(4)
+    scales = rng.integers(12, 19, size=64)
+    graphs = [gen.rmat(int(sc), 4000 + i) for i, sc in enumerate(scales)]
+    sg, ss = [], []
+    for i, g in enumerate(graphs):
+        for s in gen.random_sources(g, 4, 5000 + i):
+            sg.append(i)
+            ss.append(int(s))
+    S = sssp_mod()
+    dg = [dev(g) for g in graphs]
+    b = S.BatchSolver(dg, sg, ss)
+    b.autotune()
+    b()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            b()
+    torch.cuda.synchronize()
+    b.dist.fill_(0)
+    graph.replay()
+    torch.cuda.synchronize()
+    check(graphs, sg, ss, (b.split(b.dist), b.split(b.pred), b.split(b.pred_edge)))
