@@ -216,6 +216,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
   static_assert(FCAP % BS == 0, "FCAP must be a multiple of the block size");
 
   __shared__ int32_t s_v[FCAP];       // claimed frontier vertices
+  __shared__ uint32_t s_vd[FCAP];     // their distances (round 0)
   __shared__ uint32_t s_d[FCAP];      // gather: listed distances; relax: frontier distances
   __shared__ int32_t s_rs[FCAP];      // gather: listed vertices;  relax: first arc of each
   __shared__ int32_t s_off[FCAP + 1]; // gather: near mask per word; relax: degree prefix
@@ -415,6 +416,11 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
     const int whi = (vhi - 1) >> 5;
 
     // ------------------------------------------------ 2. gather the inbox
+    // Claim every inbox bit of the unit (one atomic and-not per word, whose
+    // result lists the claimed vertices), then load their labels: a label
+    // lowered after the claim sets its bit again.  Vertices beyond FCAP or
+    // outside the lowest bucket go back to the inbox.
+    long long claimed = 0;  // thread 0: inbox bits taken by this batch
     for (int wb = wlo; wb <= whi; wb += BS) {
       const int wi = wb + tid;
       uint32_t bits = 0;
@@ -425,23 +431,32 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
           const int hb = (vhi - 1) & 31;
           mask &= hb == 31 ? ~0u : ((1u << (hb + 1)) - 1u);
         }
-        bits = ld_rlx(&dirty[wi]) & mask;
+        if (ld_rlx(&dirty[wi]) & mask) bits = aand_acq(&dirty[wi], ~mask) & mask;
       }
       int tot;
       const int before = s_nlist;
       int j = before + block_excl_scan<BS>(__popc(bits), s_ws, &tot);
+      uint32_t back = 0;
       for (uint32_t b = bits; b; b &= b - 1) {
         if (j < FCAP) s_rs[j] = wi * 32 + __ffs(b) - 1;
+        else back |= b & (~b + 1u);
         j++;
       }
-      if (tid == 0) s_nlist = before + tot;
+      if (back) {
+        const uint32_t ob = aor(&dirty[wi], back);
+        atomicAdd(&s_new, (unsigned int)__popc(back & ~ob));
+      }
+      if (tid == 0) {
+        s_nlist = before + tot;
+        claimed += tot;
+      }
       __syncthreads();
       if (s_nlist >= FCAP) break;
     }
     const int nlist = uni(min(s_nlist, FCAP));
     const bool trunc = s_nlist > FCAP || (s_nlist == FCAP);
     if (nlist == 0) {
-      // the unit's bits were taken by another workgroup meanwhile
+      // nothing pending in the unit any more (taken by another workgroup)
       stay = -1;
       __syncthreads();
       continue;
@@ -472,35 +487,31 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
 #pragma unroll
     for (int k = 1; k < NW; k++) umin = s_red[k] < umin ? s_red[k] : umin;
     const unsigned long long T = Dist<WT>::bucket_end(umin, delta);
-    // near masks per inbox word; far minimum
+    // the lowest bucket is the frontier (with the distances just loaded);
+    // the rest goes back to the inbox, one atomic or per word
     unsigned long long far = ~0ull;
     for (int k = tid; k < nlist; k += BS) {
       const uint32_t dv = s_d[k];
       const int v = s_rs[k];
-      if ((unsigned long long)dv < T) atomicOr((unsigned int *)&s_off[(v >> 5) - wlo], 1u << (v & 31));
-      else far = dv < far ? dv : far;
+      if ((unsigned long long)dv < T) {
+        const int slot = atomicAdd(&s_cnt, 1);
+        s_v[slot] = v;
+        s_vd[slot] = dv;
+      } else {
+        far = dv < far ? dv : far;
+        atomicOr((unsigned int *)&s_off[(v >> 5) - wlo], 1u << (v & 31));
+      }
     }
     far = wave_min(far);
     if (lane == 0 && far != ~0ull) atomicMin(&s_far, far);
     __syncthreads();
-    // one atomic and-not per word (done by the first listed vertex of the
-    // word), then every listed near vertex checks whether it was claimed
-    for (int k = tid; k < nlist; k += BS) {
-      const int v = s_rs[k];
-      const int w = v >> 5;
-      if (k == 0 || (s_rs[k - 1] >> 5) != w) {
-        const uint32_t mk = (uint32_t)s_off[w - wlo];
-        if (mk) s_off[w - wlo] = (int32_t)(aand_acq(&dirty[w], ~mk) & mk);
-      }
+    unsigned int putback = 0;
+    for (int i = tid; i <= whi - wlo; i += BS) {
+      const uint32_t fb = (uint32_t)s_off[i];
+      if (fb) putback += __popc(fb & ~aor(&dirty[wlo + i], fb));
     }
-    __syncthreads();
-    for (int k = tid; k < nlist; k += BS) {
-      const int v = s_rs[k];
-      if (((uint32_t)s_off[(v >> 5) - wlo] >> (v & 31)) & 1u) {
-        if ((unsigned long long)s_d[k] < T) s_v[atomicAdd(&s_cnt, 1)] = v;
-      }
-    }
-    __syncthreads();
+    putback = wave_sum(putback);
+    if (lane == 0 && putback) atomicAdd(&s_new, putback);
     const int cnt = uni(s_cnt);
 
     // ---------------------------------------- 3-4. settle the bucket locally
@@ -535,7 +546,9 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
           const int k = k0 + j * BS + tid;
           if (k < cur_cnt) {
             const int u = s_v[k];
-            lab[j] = ld_rlx(&label[u]);
+            // round 0: the labels loaded after the claim; later rounds: the
+            // current label of each LDS-queued vertex
+            lab[j] = nround == 0 ? (unsigned long long)s_vd[k] << 32 : ld_rlx(&label[u]);
             rs[j] = row_ptr[u];
             re[j] = row_ptr[u + 1];
           }
@@ -735,7 +748,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
     // ------------------------------------------------------ 5. settle
     if (tid == 0) {
       // every consequence of this batch is published: return the surplus
-      aadd(&ctrl->work, (long long)s_new - raised - (long long)cnt);
+      aadd(&ctrl->work, (long long)s_new - raised - claimed);
       unsigned long long rem = s_far < s_lmin ? s_far : s_lmin;
       if (trunc) rem = umin < rem ? umin : rem;
       s_stay = -1;
