@@ -97,9 +97,11 @@ typedef struct {
                               average degree is >= 8 and 32768 below);
                               raised so that a block has at most 32768 vertices */
   int32_t wg_size;         /* threads per workgroup: 256, 512 or 1024; 0 = auto
-                              (cache, else 512)                            */
+                              (cache, else 512 when the average degree is
+                              >= 8 and 256 below)                          */
   int32_t num_workgroups;  /* persistent grid size; 0 = auto (cache, else one
-                              workgroup per CU); capped by residency       */
+                              workgroup per CU when the average degree is
+                              >= 8 and two below); capped by residency     */
   int32_t max_rounds;      /* > 0: stop after this many frontier batches per
                               workgroup and report SSSP_ERR_TIMEOUT; the
                               labels are then valid upper bounds           */

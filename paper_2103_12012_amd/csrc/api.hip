@@ -149,21 +149,25 @@ SolvePlan make_plan(const sssp_csr &g, const sssp_opts &o) {
     pl.delta = DELTA_AUTO;
     pl.auto_factor = auto_delta_factor(g.n, g.m);
   }
-  pl.bs = o.wg_size ? o.wg_size : (have && tuned.wg_size ? tuned.wg_size : 512);
+  // dense graphs: one 512-thread workgroup per CU (more workers mostly add
+  // contention on the unit tables and labels); sparse, high-diameter graphs
+  // with thin frontiers: two 256-thread workgroups per CU
+  const bool dense = dense_graph(g.n, g.m);
+  pl.bs = o.wg_size ? o.wg_size : (have && tuned.wg_size ? tuned.wg_size : (dense ? 512 : 256));
+  pl.grid_per_cu = dense ? 1 : 2;
   pl.grid = o.num_workgroups ? o.num_workgroups
                              : (have && tuned.num_workgroups ? tuned.num_workgroups : 0);
   pl.lag = o.lag ? o.lag : (have ? tuned.lag : 0);
   return pl;
 }
 
-// Persistent grid: the requested size (0 = one workgroup per CU), capped by
-// what can be resident at block size bs.  More workgroups than CUs mostly
-// add contention on the shared unit tables and labels.
-int plan_grid(int wtype, int bs, int want) {
+// Persistent grid: the requested size (0 = per_cu workgroups per CU), capped
+// by what can be resident at block size bs.
+int plan_grid(int wtype, int bs, int want, int per_cu_default) {
   const DevInfo di = device_info();
   const int per_cu = solve_max_blocks_per_cu(wtype, bs);
   const int resident = di.cus * per_cu;
-  if (want <= 0) want = di.cus;
+  if (want <= 0) want = di.cus * per_cu_default;
   int grid = want < resident ? want : resident;
   return grid < 1 ? 1 : grid;
 }
@@ -329,7 +333,8 @@ extern "C" int sssp_solve(const sssp_csr *g, int32_t source, const sssp_opts *o,
   d.unit0 = 0;
   d.nwords = (g->n + 31) / 32;
   opts.lag = pl.lag;
-  return run_solves(descs, L, pl.nparts, g->wtype, pl.bs, plan_grid(g->wtype, pl.bs, pl.grid),
+  return run_solves(descs, L, pl.nparts, g->wtype, pl.bs,
+                    plan_grid(g->wtype, pl.bs, pl.grid, pl.grid_per_cu),
                     opts, g, 1, stats, w, st);
 }
 
@@ -418,7 +423,7 @@ extern "C" int sssp_solve_batch(int32_t num_graphs, const sssp_csr *graphs, int3
   if (opts.wg_size) bs = opts.wg_size;
   // the grid follows the largest per-graph plan, capped by residency at bs
   if (opts.num_workgroups) grid = opts.num_workgroups;
-  grid = plan_grid(graphs[0].wtype, bs, grid);
+  grid = plan_grid(graphs[0].wtype, bs, grid, 1);
   return run_solves(descs, L, (int)nunits, graphs[0].wtype, bs, grid, opts, graphs, num_graphs,
                     stats, w, st);
 }

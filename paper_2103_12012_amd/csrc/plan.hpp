@@ -12,7 +12,8 @@ struct DevInfo {
 // Parameters of one solve after defaults and the autotune cache are applied.
 struct SolvePlan {
   int nparts = 1, bsize = 1;  // P (non-empty blocks) and block size ceil(n/P)
-  int bs = 256, grid = 1;     // workgroup size and persistent grid
+  int bs = 256, grid = 1;     // workgroup size and persistent grid (0 = default)
+  int grid_per_cu = 1;        // default grid: workgroups per CU
   unsigned long long delta = DELTA_INF;  // DELTA_AUTO: set on the device
   float auto_factor = 0.0f;              // for DELTA_AUTO
   int lag = 0;                           // window in buckets (0 = default)
