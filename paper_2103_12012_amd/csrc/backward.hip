@@ -10,6 +10,12 @@
 // child that brings the parent's count to zero continues the chain with the
 // parent.  Every vertex is finalised exactly once, with no barrier between
 // tree levels; a vertex never reached this way lies on a predecessor cycle.
+//
+// Only the part of the tree that carries gradient is walked: the vertices
+// with g != 0 and their ancestors (marked by walking up from each such
+// vertex, stopping at the first vertex already marked).  Every other arc's
+// gradient is zero.  A sparse upstream gradient (a loss over a few targets)
+// thus touches only the union of the targets' tree paths.
 #include "internal.hpp"
 #include "launch.hpp"
 
@@ -26,6 +32,7 @@ struct BwdArgs {
   int32_t *par;       // tail of pred_edge[v], -1 for the source / unreached
   int32_t *nchild;    // children not yet finalised
   int32_t *leaf;      // 1 when v starts a chain
+  int32_t *mark;      // 1 when v carries gradient (g != 0 below it)
   double *acc;        // subtree totals
   unsigned long long *counts;  // [0] reached vertices != s, [1] finalised
   int32_t *status;
@@ -36,20 +43,22 @@ __global__ void k_bwd_zero(BwdArgs a) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int stride = gridDim.x * blockDim.x;
   for (int e = t; e < a.m; e += stride) a.grad_w[e] = 0.0f;
-  for (int v = t; v < a.n; v += stride) a.nchild[v] = 0;
+  for (int v = t; v < a.n; v += stride) {
+    a.nchild[v] = 0;
+    a.mark[v] = 0;
+  }
   if (t == 0) {
     a.counts[0] = 0;
     a.counts[1] = 0;
   }
 }
 
-// Parent of every reached v != s (binary search of its pred arc's tail),
-// child counts and the starting totals acc[v] = g[v].
+// Parent of every reached v != s (binary search of its pred arc's tail) and
+// the starting totals acc[v] = g[v].
 __global__ void k_bwd_parent(BwdArgs a) {
   if (*a.status) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int stride = gridDim.x * blockDim.x;
-  unsigned long long reached = 0;
   for (int v = t; v < a.n; v += stride) {
     int p = -1;
     double g0 = 0.0;
@@ -66,23 +75,53 @@ __global__ void k_bwd_parent(BwdArgs a) {
           else hi = mid - 1;
         }
         p = lo;
-        reached++;
         g0 = (double)a.g[v];
-        if (p != a.source) atomicAdd(&a.nchild[p], 1);
       }
     }
     a.par[v] = p;
     a.acc[v] = g0;
   }
-  reached = wave_sum(reached);
-  if (lane_id() == 0 && reached) aadd(&a.counts[0], reached);
+}
+
+// Marks every vertex with g != 0 and its ancestors: a walk up the tree stops
+// at the source or at the first vertex some walk has marked already.  The
+// number of marked vertices is counts[0].
+__global__ void k_bwd_mark(BwdArgs a) {
+  if (*a.status) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int stride = gridDim.x * blockDim.x;
+  unsigned long long marked = 0;
+  for (int v = t; v < a.n; v += stride) {
+    if (a.par[v] < 0 || a.acc[v] == 0.0) continue;
+    int x = v;
+    for (;;) {
+      if (__hip_atomic_fetch_or(&a.mark[x], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+      marked++;
+      const int p = a.par[x];
+      if (p == a.source || p < 0) break;
+      x = p;
+    }
+  }
+  marked = wave_sum(marked);
+  if (lane_id() == 0 && marked) aadd(&a.counts[0], marked);
+}
+
+// Children that carry gradient, per parent.
+__global__ void k_bwd_count(BwdArgs a) {
+  if (*a.status) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int stride = gridDim.x * blockDim.x;
+  for (int v = t; v < a.n; v += stride) {
+    const int p = a.par[v];
+    if (a.mark[v] && p >= 0 && p != a.source) atomicAdd(&a.nchild[p], 1);
+  }
 }
 
 __global__ void k_bwd_leaves(BwdArgs a) {
   if (*a.status) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int stride = gridDim.x * blockDim.x;
-  for (int v = t; v < a.n; v += stride) a.leaf[v] = a.par[v] >= 0 && a.nchild[v] == 0;
+  for (int v = t; v < a.n; v += stride) a.leaf[v] = a.mark[v] && a.par[v] >= 0 && a.nchild[v] == 0;
 }
 
 __global__ void k_bwd_chain(BwdArgs a) {
@@ -133,6 +172,7 @@ size_t backward_ws_bytes(int n) {
   take(4ull * n);
   take(4ull * n);
   take(4ull * n);
+  take(4ull * n);
   take(8ull * n);
   take(256);
   return b;
@@ -160,6 +200,7 @@ int launch_backward(const sssp_csr &g, int source, const float *dist, const int3
   a.par = reinterpret_cast<int32_t *>(take(4ull * g.n));
   a.nchild = reinterpret_cast<int32_t *>(take(4ull * g.n));
   a.leaf = reinterpret_cast<int32_t *>(take(4ull * g.n));
+  a.mark = reinterpret_cast<int32_t *>(take(4ull * g.n));
   a.acc = reinterpret_cast<double *>(take(8ull * g.n));
   char *misc = take(256);
   a.counts = reinterpret_cast<unsigned long long *>(misc);
@@ -174,6 +215,8 @@ int launch_backward(const sssp_csr &g, int source, const float *dist, const int3
   if (validate && launch_validate(g, 0, 1, a.status, st) != hipSuccess) return SSSP_ERR_HIP;
   hipLaunchKernelGGL(k_bwd_zero, dim3(blocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_bwd_parent, dim3(vblocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_bwd_mark, dim3(vblocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_bwd_count, dim3(vblocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_bwd_leaves, dim3(vblocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_bwd_chain, dim3(vblocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_bwd_check, dim3(1), dim3(64), 0, st, a, stats);
