@@ -9,8 +9,10 @@ per second of step time.  Inputs are resident in HBM before timing starts.
 
 Extra measurements on the same GPU (reported under "extra"): the road-like
 4096x4096 grid solve, the batched solve (64 R-MAT graphs of scales 12..18,
-4 sources each, one captured launch) against 256 single-source calls, and
-the differentiable R-MAT scale-22 forward + backward.
+4 sources each, one captured launch) against 256 single-source calls, the
+differentiable R-MAT scale-22 forward + backward, and an ablation of the
+local rule (bucket width 1 = exact local distance order, one unbounded
+bucket = asynchronous Bellman-Ford, automatic width) on the headline graph.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only NAME ...]
 """
@@ -400,6 +402,41 @@ def bench_diff(steps):
             "tolerance": "1e-5 rel dist (bit-exact expected), 1e-4 grad"}
 
 
+def bench_ablation(steps):
+    """Local rule ablation on the pruned R-MAT 20 graph (256 partitions): the
+    bucket width decides how literally each partition follows Alg. 3.
+    delta = 1 on integer costs settles every partition in exact distance
+    order (a bucket queue: the local Dijkstra order), delta = -1 is one
+    unbounded bucket (fully asynchronous Bellman-Ford), 0 is the automatic
+    width.  Same graph, source and partitions as the headline step."""
+    import torch
+
+    from paper_2103_12012_amd import gen, sssp
+
+    g = gen.rmat(20, 20)
+    s = int(gen.random_sources(g, 1, 20)[0])
+    rp, c, w = sssp.to_device(g, "cuda")
+    keep, (prp, pc, pw, emap) = sssp.prune(rp, c, w, num_partitions=256, validate=False)
+    torch.cuda.synchronize()
+    kept = int(prp[-1].item())
+    ev = HipEvents()
+    out = {"workload": "rmat20_pruned_local_rule", "partitions": 256}
+    for name, delta, lag in (("dijkstra_order_delta1", 1.0, -1), ("dijkstra_order_delta1_lag1", 1.0, 1),
+                             ("async_bellman_ford", -1.0, 0), ("auto", 0.0, 0)):
+        solver = sssp.Solver(prp, pc[:kept], pw[:kept], num_partitions=256, delta=delta,
+                             lag=lag, validate=False, stats=True, no_autotune=True)
+        ts = []
+        for _ in range(max(2, steps)):
+            e = ev.pair()
+            solver(s, events=e)
+            ts.append(ev.ms(e))
+        st = solver.stats.read()
+        out[name] = {"solve_ms": float(np.median(ts)), "edges_relaxed": st["edges_relaxed"],
+                     "label_updates": st["label_updates"],
+                     "vertices_expanded": st["vertices_expanded"], "batches": st["batches"]}
+    return out
+
+
 def bench_copy(steps):
     """A plain device copy of 1 GiB: the calibration that scales the
     FETCH_SIZE / WRITE_SIZE counters to bytes (each reads 1 GiB ideally)."""
@@ -426,8 +463,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--only", nargs="*", default=None,
-                    help="subset of: rmat20 grid batch diff copy (copy: counter calibration, "
-                         "not part of the default run)")
+                    help="subset of: rmat20 grid batch diff ablation copy (copy: counter "
+                         "calibration, not part of the default run)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -438,7 +475,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    only = set(args.only) if args.only else {"rmat20", "grid", "batch", "diff"}
+    only = set(args.only) if args.only else {"rmat20", "grid", "batch", "diff", "ablation"}
     extra = {}
     head = None
     if "rmat20" in only:
@@ -446,7 +483,7 @@ def main():
         print(f"[bench] rmat20 done: {head['ms_per_step']:.3f} ms/step", file=sys.stderr,
               flush=True)
     for name, fn in (("grid", bench_grid), ("batch", bench_batch), ("diff", bench_diff),
-                     ("copy", bench_copy)):
+                     ("ablation", bench_ablation), ("copy", bench_copy)):
         if name in only:
             extra[name] = fn(max(1, min(args.steps, 5)))
             print(f"[bench] {name} done", file=sys.stderr, flush=True)
