@@ -26,8 +26,8 @@
 //  * N_in(x) comes from a CSC (in-lists) built here by a counting sort;
 //  * a table owner with a short list and little work is handled by one
 //    wavefront with a private LDS table; heavier owners are split into
-//    workgroup items of about HV_TARGET estimated probes, in three tiers by
-//    list length (LDS tables of 1024 and 4096 slots for 256-thread
+//    workgroup items of about HV_TARGET estimated probes, in four tiers by
+//    list length (LDS tables of 1024, 2048 and 4096 slots for 256-thread
 //    workgroups, 16384 slots for 1024-thread workgroups, or an L2-resident
 //    global table when the list exceeds HV_TCAP entries), so that short
 //    tables leave room for more resident workgroups.
@@ -47,15 +47,25 @@ constexpr int LT_DEG = 128;          // light owner: list length
 constexpr int LT_SLOTS = 256;        // light owner: wave-private hash slots
 constexpr int LT_WORK = 8192;        // light owner: probes
 constexpr int LT_BS = 256;
-constexpr int HS_TCAP = 512;         // small heavy owner: longest list
+// heavy tiers by list length: LDS tables of 2x the longest list (load <= 1/2)
+constexpr int NTIER = 4;
+constexpr int T_BIG = NTIER - 1;      // big owners: 1024-thread items
+constexpr int HS_TCAP = 512;          // tier 0: longest list
 constexpr int HS_SLOTS = 1024;
-constexpr int HM_TCAP = 2048;        // medium heavy owner: longest list
+constexpr int HM1_TCAP = 1024;        // tier 1
+constexpr int HM1_SLOTS = 2048;
+constexpr int HM_TCAP = 2048;         // tier 2
 constexpr int HM_SLOTS = 4096;
+// ticket counters: [0, NTIER) heavy items per tier, then the sort queues
+// and the light owners
+constexpr int TK_SORT_SHORT = NTIER, TK_SORT_LONG = NTIER + 1, TK_LIGHT = NTIER + 2;
 constexpr int HM_BS = 256;
 constexpr int HM_Q = 256;            // medium: arcs staged per batch
+constexpr int HM_MARKS = 1024;       // medium: slot marks of a round
 constexpr int HV_TCAP = 8192;        // big heavy owner: longest list in an LDS table
 constexpr int HV_SLOTS = 16384;
 constexpr int HV_Q = 512;            // big: arcs staged per batch
+constexpr int HV_MARKS = 2048;       // big: slot marks of a round
 constexpr int ITEM_MINQ = 32;        // an item covers at least this many arcs
 constexpr int HV_TARGET = 1 << 18;   // heavy: estimated probes per item
 constexpr int SORT_MIN = 16;         // lists of SORT_MIN+1 .. SORT_MAX entries
@@ -93,27 +103,30 @@ struct TbArgs {
   const uint32_t *w;
   int n, m, local, bsize;
   uint8_t *keep;
-  int rep;          // R: replicas of every column counter (spreads hub contention)
+  int cs, nb;       // CSC build: buckets of heads x >> cs, nb of them
+  int ct;           // CSC build: arcs per tile
   int32_t *src;     // m: tail of every arc
-  int32_t *cnt;     // n*R: in-degree replicas
-  int32_t *cptr;    // n*R+1: CSC offsets per replica (column x starts at cptr[x*R])
+  int32_t *btot;    // nb: arcs per bucket
+  int32_t *bfill;   // nb: arcs placed per bucket
+  int32_t *bstart;  // nb+1: bucket offsets in stage
+  int4 *stage;      // m: arcs (x, u, cost, e) grouped by bucket (aliases gkey)
+  int32_t *ccnt;    // n: in-degrees
+  int32_t *cfill;   // n: CSC entries placed per column
   int32_t *cb;      // n+1: column x is [cb[x], cb[x+1])
-  int32_t *rank;    // m: position of arc e among the arcs of its column replica
   int2 *cyw;        // m: CSC entries (tail, cost); sorted lists by cost
   int32_t *ceid;    // m: CSC -> CSR edge id (moves with cyw)
   int2 *rs;         // m: CSR rows as (head, cost); sorted lists by cost
   int32_t *sl;      // 2n: lists to sort, short ones from the front, long
                     //     ones (> SORT_WAVE entries) from the back
   int32_t *work;    // 2n: probes of owner i (i < n: in-table of i; else out-table of i-n)
-  int32_t *hflag;   // 2n: 0 light, 1 medium, 2 big heavy owner
-  HList hl[3];      // heavy owners: [0] small, [1] medium, [2] big
+  int32_t *hflag;   // 2n: 0 light or no work, else heavy tier + 1
+  HList hl[NTIER];  // heavy owners per tier (T_BIG: the longest lists)
   int32_t *gsz;     // 2n: global table size in units of G_UNIT slots (0 = LDS)
   int32_t *goff;    // 2n+1: exclusive scan of gsz
   int32_t *gkey;    // global tables: keys (-1 = empty)
   uint32_t *gval;   //                cheapest parallel arc
   int32_t *llist;   // 2n: light owners (order of appending)
-  int32_t *tickets; // [0..2] heavy items per tier, [3] short and [4] long
-                    // lists to sort, [5] light owners
+  int32_t *tickets; // TK_* counters
   int32_t *status;
   sssp_stats *stats;
 };
@@ -163,7 +176,7 @@ __device__ __forceinline__ void wave_sync() {
 __global__ void k_tb_status(TbArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *a.status = 0;
-    for (int k = 0; k < 6; k++) a.tickets[k] = 0;
+    for (int k = 0; k <= TK_LIGHT; k++) a.tickets[k] = 0;
   }
   if (a.stats && blockIdx.x == 0 && threadIdx.x < (int)(sizeof(sssp_stats) / 4))
     reinterpret_cast<uint32_t *>(a.stats)[threadIdx.x] = 0u;
@@ -172,23 +185,22 @@ __global__ void k_tb_status(TbArgs a) {
 __device__ __forceinline__ int cbeg(const TbArgs &a, int x) { return a.cb[x]; }
 __device__ __forceinline__ int clen(const TbArgs &a, int x) { return a.cb[x + 1] - a.cb[x]; }
 
-__global__ void k_tb_cols(TbArgs a) {
-  if (*a.status) return;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int stride = gridDim.x * blockDim.x;
-  for (int x = t; x <= a.n; x += stride) a.cb[x] = a.cptr[(long long)x * a.rep];
-}
-
 __global__ void k_tb_zero(TbArgs a) {
   if (*a.status) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int stride = gridDim.x * blockDim.x;
   for (int e = t; e < a.m; e += stride) a.keep[e] = 1;
-  const long long nr = (long long)a.n * a.rep;
-  for (long long i = t; i < nr; i += stride) a.cnt[i] = 0;
+  for (int i = t; i < a.n; i += stride) {
+    a.ccnt[i] = 0;
+    a.cfill[i] = 0;
+  }
+  for (int i = t; i < a.nb; i += stride) {
+    a.btot[i] = 0;
+    a.bfill[i] = 0;
+  }
   for (int i = t; i < 2 * a.n; i += stride) {
     a.work[i] = 0;
-    for (int k = 0; k < 3; k++) a.hl[k].items[i] = 0;
+    for (int k = 0; k < NTIER; k++) a.hl[k].items[i] = 0;
   }
 }
 
@@ -203,41 +215,135 @@ __global__ void k_tb_tails(TbArgs a) {
   }
 }
 
-__device__ __forceinline__ int rep_of(const TbArgs &a, int e) { return e & (a.rep - 1); }
+// ------------------------------------------------------------------ CSC
+// The in-lists come from a two-level counting sort of the arcs by head x,
+// built so that almost every atomic lands in LDS:
+//  * level 1 groups the arcs by bucket x >> cs (at most CB_MAX buckets) in
+//    a staging array: a tile of ct arcs counts its buckets in LDS and
+//    reserves its run of every nonempty bucket with one global atomic;
+//  * level 2 takes the staged arcs in chunks of CCH.  A chunk holds a short
+//    run of buckets, so its heads fall in a window of CW columns (counted in
+//    LDS) but for a few in sparse regions (one global atomic each).  A
+//    first pass adds the chunk's column counts into the in-degrees; after
+//    their scan (the column offsets) a second pass reserves the chunk's run
+//    of every column and places the entries.
+// The order inside a column is arbitrary; columns are sorted by cost later.
+constexpr int CB_MAX = 4096;   // level-1 buckets
+constexpr int C_BS = 1024;
+constexpr int C_TILES = 512;   // level-1 tiles (at most)
+constexpr int CCH = 8192;      // level-2 chunk of staged arcs
+constexpr int CW = 4096;       // level-2 LDS column window
 
-// Thread per arc: count the in-degree replicas; the count before the arc is
-// its rank within its column replica.
-__global__ void k_tb_indeg(TbArgs a) {
+__device__ __forceinline__ int stage_x(const TbArgs &a, int p) {
+  return reinterpret_cast<const int32_t *>(a.stage)[4ll * p];
+}
+
+// Level 1, pass 1: bucket sizes (and the head range check).
+__global__ __launch_bounds__(C_BS) void k_csc_hist(TbArgs a) {
+  __shared__ int s_h[CB_MAX];
   if (*a.status) return;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int stride = gridDim.x * blockDim.x;
-  for (int e = t; e < a.m; e += stride) {
+  for (int b = threadIdx.x; b < a.nb; b += C_BS) s_h[b] = 0;
+  __syncthreads();
+  const int e0 = blockIdx.x * a.ct;
+  const int e1 = (int)min((long long)a.m, (long long)e0 + a.ct);
+  for (int e = e0 + threadIdx.x; e < e1; e += C_BS) {
     const int x = a.col[e];
-    if ((unsigned)x < (unsigned)a.n) {
-      a.rank[e] = atomicAdd(&a.cnt[(long long)x * a.rep + rep_of(a, e)], 1);
-    } else {
-      a.rank[e] = 0;
-      set_status(a.status, SSSP_ERR_CSR);
-    }
+    if ((unsigned)x < (unsigned)a.n) atomicAdd(&s_h[x >> a.cs], 1);
+    else set_status(a.status, SSSP_ERR_CSR);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < a.nb; b += C_BS)
+    if (s_h[b]) atomicAdd(&a.btot[b], s_h[b]);
+}
+
+// Level 1, pass 2: reserve the tile's run of every bucket, stage the arcs,
+// and copy the rows as (head, cost).
+__global__ __launch_bounds__(C_BS) void k_csc_scatter(TbArgs a) {
+  __shared__ int s_h[CB_MAX];
+  if (*a.status) return;
+  for (int b = threadIdx.x; b < a.nb; b += C_BS) s_h[b] = 0;
+  __syncthreads();
+  const int e0 = blockIdx.x * a.ct;
+  const int e1 = (int)min((long long)a.m, (long long)e0 + a.ct);
+  for (int e = e0 + threadIdx.x; e < e1; e += C_BS) atomicAdd(&s_h[a.col[e] >> a.cs], 1);
+  __syncthreads();
+  for (int b = threadIdx.x; b < a.nb; b += C_BS)
+    if (s_h[b]) s_h[b] = a.bstart[b] + atomicAdd(&a.bfill[b], s_h[b]);
+  __syncthreads();
+  for (int e = e0 + threadIdx.x; e < e1; e += C_BS) {
+    const int x = a.col[e];
+    const int u = a.src[e];
+    const int wv = (int)a.w[e];
+    a.rs[e] = make_int2(x, wv);
+    a.stage[atomicAdd(&s_h[x >> a.cs], 1)] = make_int4(x, u, wv, e);
   }
 }
 
-// Thread per arc: scatter into the CSC at its replica's offset plus its
-// rank (no atomics), and copy the row entries.
-__global__ void k_tb_fill(TbArgs a) {
+__device__ __forceinline__ int chunk_x0(const TbArgs &a, int p0) {
+  return (stage_x(a, p0) >> a.cs) << a.cs;
+}
+
+// Level 2, pass 1: in-degrees.
+__global__ __launch_bounds__(C_BS) void k_csc_count(TbArgs a) {
+  __shared__ int s_c[CW];
   if (*a.status) return;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int stride = gridDim.x * blockDim.x;
-  for (int e = t; e < a.m; e += stride) {
-    const int x = a.col[e];
-    const int u = a.src[e];
-    const uint32_t wv = a.w[e];
-    const long long c = (long long)x * a.rep + rep_of(a, e);
-    const int pos = a.cptr[c] + a.rank[e];
-    a.cyw[pos] = make_int2(u, (int)wv);
-    a.ceid[pos] = e;
-    a.rs[e] = make_int2(x, (int)wv);
+  const int p0 = blockIdx.x * CCH;
+  const int p1 = (int)min((long long)a.m, (long long)p0 + CCH);
+  const int x0 = chunk_x0(a, p0);
+  for (int c = threadIdx.x; c < CW; c += C_BS) s_c[c] = 0;
+  __syncthreads();
+  for (int p = p0 + threadIdx.x; p < p1; p += C_BS) {
+    const int x = stage_x(a, p);
+    if (x - x0 < CW) atomicAdd(&s_c[x - x0], 1);
+    else atomicAdd(&a.ccnt[x], 1);
   }
+  __syncthreads();
+  const int cw = min(CW, a.n - x0);
+  for (int c = threadIdx.x; c < cw; c += C_BS)
+    if (s_c[c]) atomicAdd(&a.ccnt[x0 + c], s_c[c]);
+}
+
+// Level 2, pass 2: place the entries at their column offsets, and charge
+// the x-side probes of every arc to its column's table owner: an arc
+// (u, x) with |N_out(u)| <= |N_in(x)| scans N_out(u).
+__global__ __launch_bounds__(C_BS) void k_csc_place(TbArgs a) {
+  __shared__ int s_c[CW];  // counts, then cursors
+  __shared__ int s_w[CW];  // probes
+  if (*a.status) return;
+  const int p0 = blockIdx.x * CCH;
+  const int p1 = (int)min((long long)a.m, (long long)p0 + CCH);
+  const int x0 = chunk_x0(a, p0);
+  const int cw = min(CW, a.n - x0);
+  for (int c = threadIdx.x; c < CW; c += C_BS) {
+    s_c[c] = 0;
+    s_w[c] = 0;
+  }
+  __syncthreads();
+  for (int p = p0 + threadIdx.x; p < p1; p += C_BS) {
+    const int x = stage_x(a, p);
+    if (x - x0 < CW) atomicAdd(&s_c[x - x0], 1);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < cw; c += C_BS)
+    if (s_c[c]) s_c[c] = a.cb[x0 + c] + atomicAdd(&a.cfill[x0 + c], s_c[c]);
+  __syncthreads();
+  for (int p = p0 + threadIdx.x; p < p1; p += C_BS) {
+    const int4 r = a.stage[p];
+    const int x = r.x, u = r.y;
+    const bool win = x - x0 < CW;
+    const int pos = win ? atomicAdd(&s_c[x - x0], 1) : a.cb[x] + atomicAdd(&a.cfill[x], 1);
+    a.cyw[pos] = make_int2(u, r.z);
+    a.ceid[pos] = r.w;
+    const int ou = a.row_ptr[u + 1] - a.row_ptr[u];
+    const int val = ou <= a.cb[x + 1] - a.cb[x] ? ou : 0;
+    if (val) {
+      if (win) atomicAdd(&s_w[x - x0], val);
+      else atomicAdd(&a.work[x], val);
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < cw; c += C_BS)
+    if (s_w[c]) atomicAdd(&a.work[x0 + c], s_w[c]);
 }
 
 // ------------------------------------------------------------------ sort
@@ -307,7 +413,7 @@ __global__ __launch_bounds__(CLS_BS) void k_tb_sort_class(TbArgs a) {
     if (threadIdx.x < 2) {
       int tot = 0;
       for (int w = 0; w < CLS_BS / WAVE; w++) tot += s_cnt[threadIdx.x][w];
-      s_base[threadIdx.x] = tot ? atomicAdd(&a.tickets[3 + threadIdx.x], tot) : 0;
+      s_base[threadIdx.x] = tot ? atomicAdd(&a.tickets[TK_SORT_SHORT + threadIdx.x], tot) : 0;
     }
     __syncthreads();
     int offs = s_base[0], offl = s_base[1];
@@ -394,7 +500,7 @@ __global__ void k_tb_sort_small(TbArgs a) {
   if (*a.status) return;
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int nwaves = gridDim.x * blockDim.x / WAVE;
-  const int ns = a.tickets[3];
+  const int ns = a.tickets[TK_SORT_SHORT];
   for (int j = wave; j < ns; j += nwaves) {
     const SortSeg g = sort_seg(a, a.sl[j]);
     if (g.len <= WAVE) wave_sort_list<1>(a, g);
@@ -412,7 +518,7 @@ __global__ __launch_bounds__(SORT_BS) void k_tb_sort_mid(TbArgs a) {
   __shared__ int sp[SORT_MAX];
   if (*a.status) return;
   const int tid = threadIdx.x;
-  const int nl = a.tickets[4];
+  const int nl = a.tickets[TK_SORT_LONG];
   for (int j = blockIdx.x; j < nl; j += gridDim.x) {
     const SortSeg g = sort_seg(a, a.sl[2 * a.n - 1 - j]);
     int N = 2 * SORT_WAVE;
@@ -489,9 +595,10 @@ __device__ __forceinline__ void seg_add(int32_t *work, bool active, int key, int
   }
 }
 
-// Probes each arc costs, charged to its table owner: the u-side arcs of row
-// u add |N_in(x)| to owner n+u (one thread per arc), the x-side arcs of
-// column x add |N_out(u)| to owner x (one thread per CSC entry).
+// Probes of the u-side arcs, charged to their table owner: an arc (u, x)
+// with |N_out(u)| > |N_in(x)| scans N_in(x) against the table of N_out(u),
+// owner n+u (one thread per arc; the x-side arcs are charged while the CSC
+// is placed).
 __global__ void k_tb_work(TbArgs a) {
   if (*a.status) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -507,17 +614,6 @@ __global__ void k_tb_work(TbArgs a) {
       val = ou > ix ? ix : 0;
     }
     seg_add(a.work + a.n, act, u, val);
-  }
-  for (int p = t; p < mr; p += stride) {
-    const bool act = p < a.m;
-    int x = -1, val = 0;
-    if (act) {
-      const int u = a.cyw[p].x;
-      x = a.col[a.ceid[p]];
-      const int ou = a.row_ptr[u + 1] - a.row_ptr[u];
-      val = ou <= clen(a, x) ? ou : 0;
-    }
-    seg_add(a.work, act, x, val);
   }
 }
 
@@ -550,20 +646,19 @@ __global__ __launch_bounds__(CLF_BS) void k_tb_classify(TbArgs a) {
     if (threadIdx.x == 0) {
       int tot = 0;
       for (int w = 0; w < CLF_BS / WAVE; w++) tot += s_cnt[w];
-      s_base = tot ? atomicAdd(&a.tickets[5], tot) : 0;
+      s_base = tot ? atomicAdd(&a.tickets[TK_LIGHT], tot) : 0;
     }
     __syncthreads();
     int off = s_base;
     for (int w = 0; w < wid; w++) off += s_cnt[w];
     if (light) a.llist[off + __popcll(bl & ((1ull << lane) - 1ull))] = i;
     if (in) {
-      const int tier = !heavy ? 0 : (len > HM_TCAP ? 3 : (len > HS_TCAP ? 2 : 1));
-      a.hflag[i] = tier;
-      a.hl[0].flag[i] = tier == 1;
-      a.hl[1].flag[i] = tier == 2;
-      a.hl[2].flag[i] = tier == 3;
+      // hflag = heavy tier + 1 (0 = light or no work)
+      const int tier = len > HM_TCAP ? T_BIG : (len > HM1_TCAP ? 2 : (len > HS_TCAP ? 1 : 0));
+      a.hflag[i] = heavy ? tier + 1 : 0;
+      for (int k = 0; k < NTIER; k++) a.hl[k].flag[i] = heavy && tier == k;
       int g = 0;
-      if (tier == 3 && len > HV_TCAP) g = (1 << tb_bits(len, 6)) / G_UNIT;
+      if (heavy && tier == T_BIG && len > HV_TCAP) g = (1 << tb_bits(len, 6)) / G_UNIT;
       a.gsz[i] = g;
     }
     __syncthreads();
@@ -592,7 +687,7 @@ __global__ void k_tb_item_map(TbArgs a) {
   if (*a.status) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int stride = gridDim.x * blockDim.x;
-  for (int tier = 0; tier < 3; tier++) {
+  for (int tier = 0; tier < NTIER; tier++) {
     const HList &h = a.hl[tier];
     const int nh = h.pos[2 * a.n];
     for (int j = t; j < nh; j += stride) {
@@ -618,7 +713,7 @@ __global__ void k_tb_gclear(TbArgs a) {
 
 __global__ __launch_bounds__(256) void k_tb_gtab(TbArgs a) {
   if (*a.status) return;
-  const HList &h = a.hl[2];
+  const HList &h = a.hl[T_BIG];
   const int nh = h.pos[2 * a.n];
   for (int j = blockIdx.x; j < nh; j += gridDim.x) {
     const int i = h.id[j];
@@ -725,22 +820,41 @@ __device__ __forceinline__ int tb_check(const TbArgs &a, const Owner &o, int2 yw
   return 0;
 }
 
-// Last q < nq with off[q] <= idx, galloping forward from hint.
-__device__ __forceinline__ int locate(const int32_t *off, int nq, int idx, int &hint) {
-  int qlo = hint, step = 1;
-  while (qlo + step < nq && off[qlo + step] <= idx) {
-    qlo += step;
-    step <<= 1;
+// A round lays the chunks of its live arcs end to end: live slot s holds
+// arc sq[s], entries [soff[s], soff[s+1]) (soff[nlive] = total, every
+// slot nonempty).  mark[k] is the slot holding entry k << gshift (and the
+// mark after the last one is nlive - 1), so the slot of an entry lies
+// between two marks: a binary search over a range that is almost always
+// one or two slots.
+__device__ __forceinline__ int locate(const int32_t *mark, int gshift, const int32_t *soff,
+                                      int idx) {
+  const int k = idx >> gshift;
+  int lo = mark[k], hi = mark[k + 1];
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (soff[mid] <= idx) lo = mid;
+    else hi = mid - 1;
   }
-  int qhi = min(qlo + step, nq) - 1;
-  while (qlo < qhi) {
-    const int mid = (qlo + qhi + 1) >> 1;
-    if (off[mid] <= idx) qlo = mid;
-    else qhi = mid - 1;
-  }
-  hint = qlo;
-  return qlo;
+  return lo;
 }
+
+// Mark spacing 2^g: at most nmarks marks, and at most 8 (+1) per arc of a
+// round with chunks of up to D entries (one thread writes an arc's marks).
+__device__ __forceinline__ int mark_shift(int tot, int nmarks, int D) {
+  int g = 0;
+  while (((tot - 1) >> g) + 1 > nmarks || (D >> g) > 8) g++;
+  return g;
+}
+
+// Live slot of arc q (chunk of c > 0 entries at off): its marks.
+__device__ __forceinline__ void put_marks(int32_t *mark, int gshift, int slot, int off, int c) {
+  for (int k = (off + (1 << gshift) - 1) >> gshift; (k << gshift) < off + c; k++) mark[k] = slot;
+}
+
+// Packs a chunk length with a live count for one prefix scan: sums stay
+// below 2^31 for at most 1024 arcs of chunks below 2^20 in total.
+constexpr int LIVE_SH = 20;
+__device__ __forceinline__ int live_pack(int c) { return c > 0 ? (1 << LIVE_SH) | c : 0; }
 
 // Scan limit of an arc in LDS: entries at list positions >= limit are not
 // examined.  A cost stop at f lowers it to f (entries before f may still
@@ -760,13 +874,13 @@ constexpr int SCAN_U = 4;  // scanned entries loaded ahead per lane
 // staged arcs (LDS arrays of one batch): SCAN_U loads in flight per lane.
 template <int WT>
 __device__ __forceinline__ void scan_entries(const TbArgs &a, const Owner &o, int first,
-                                             int step, int tot, int nq, const int32_t *qoff,
+                                             int step, int tot, const int32_t *mark, int gshift,
+                                             const int32_t *soff, const int32_t *sq,
                                              const int32_t *qcur, int32_t *qlim,
                                              const int32_t *qother, const uint32_t *qW,
                                              const int32_t *qeid, const int32_t *tkey,
                                              const uint32_t *tval, int tmask, int tbits) {
   const int2 *list = o.mode == 0 ? a.rs : a.cyw;
-  int hint = 0;
   for (int base = first; base < tot; base += SCAN_U * step) {
     int q[SCAN_U], f[SCAN_U];
     int2 yw[SCAN_U];
@@ -776,8 +890,9 @@ __device__ __forceinline__ void scan_entries(const TbArgs &a, const Owner &o, in
       f[u] = -1;
       q[u] = 0;
       if (idx < tot) {
-        q[u] = locate(qoff, nq, idx, hint);
-        const int fu = qcur[q[u]] + (idx - qoff[q[u]]);
+        const int sl = locate(mark, gshift, soff, idx);
+        q[u] = sq[sl];
+        const int fu = qcur[q[u]] + (idx - soff[sl]);
         if (fu < ld_lim(&qlim[q[u]])) {
           f[u] = fu;
           yw[u] = list[fu];
@@ -794,22 +909,27 @@ __device__ __forceinline__ void scan_entries(const TbArgs &a, const Owner &o, in
   }
 }
 
-template <int SLOTS, int QN>
+template <int SLOTS, int QN, int NM>
 struct TbHeavy {
   int32_t key[SLOTS];
   uint32_t val[SLOTS];
   int32_t qcur[QN];    // next list position to scan
-  int32_t qoff[QN + 1];
+  int32_t soff[QN + 1];  // live slots of the round: entry offsets,
+  int32_t sq[QN];        //   arcs,
+  int32_t mark[NM + 1];  //   and marks
   uint32_t qW[QN];
   int32_t qeid[QN];
   int32_t qother[QN];  // other end | UNSORTED
   int32_t qlim[QN];    // scan limit
 };
+constexpr int LT_MARKS = 128;
 struct TbLight {         // one per wave
   int32_t key[LT_SLOTS];
   uint32_t val[LT_SLOTS];
   int32_t qcur[WAVE];
-  int32_t qoff[WAVE + 1];
+  int32_t soff[WAVE + 1];
+  int32_t sq[WAVE];
+  int32_t mark[LT_MARKS + 1];
   uint32_t qW[WAVE];
   int32_t qeid[WAVE];
   int32_t qother[WAVE];
@@ -819,9 +939,10 @@ struct TbLight {         // one per wave
 // Heavy owners of one tier: workgroup items taken from a ticket counter;
 // the owner's table is in LDS (SLOTS slots) or, for the longest lists of
 // the big tier, in global memory.
-template <int WT, int TIER, int BS, int SLOTS, int QN>
+template <int WT, int TIER, int BS, int SLOTS, int QN, int NM>
 __global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
-  __shared__ TbHeavy<SLOTS, QN> H;
+  static_assert(QN <= BS && QN <= 1024 && (long long)QN * Q_DMAX < (1 << LIVE_SH), "packing");
+  __shared__ TbHeavy<SLOTS, QN, NM> H;
   __shared__ int s_ws[BS / WAVE + 1];
   __shared__ int s_t;
   if (*a.status) return;
@@ -844,7 +965,7 @@ __global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
     const int32_t *tkey;
     const uint32_t *tval;
     int tbits;
-    if (TIER == 2 && a.gsz[i]) {
+    if (TIER == T_BIG && a.gsz[i]) {
       const long long base = (long long)a.goff[i] * G_UNIT;
       tkey = a.gkey + base;
       tval = a.gval + base;
@@ -883,14 +1004,24 @@ __global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
       for (int D = Q_D0;; D = min(2 * D, Q_DMAX)) {
         int c = 0;
         if (tid < nq) c = max(0, min(D, H.qlim[tid] - H.qcur[tid]));
-        int tot;
-        const int run = block_excl_scan<BS>(c, s_ws, &tot);
+        int packed;
+        const int run = block_excl_scan<BS>(live_pack(c), s_ws, &packed);
+        const int tot = packed & ((1 << LIVE_SH) - 1);
         if (tot == 0) break;
-        if (tid < nq) H.qoff[tid] = run;
-        if (tid == 0) H.qoff[nq] = tot;
+        const int gshift = mark_shift(tot, NM, D);
+        if (c > 0) {
+          const int sl = run >> LIVE_SH, off = run & ((1 << LIVE_SH) - 1);
+          H.sq[sl] = tid;
+          H.soff[sl] = off;
+          put_marks(H.mark, gshift, sl, off, c);
+        }
+        if (tid == 0) {
+          H.soff[packed >> LIVE_SH] = tot;
+          H.mark[((tot - 1) >> gshift) + 1] = (packed >> LIVE_SH) - 1;
+        }
         __syncthreads();
-        scan_entries<WT>(a, o, tid, BS, tot, nq, H.qoff, H.qcur, H.qlim, H.qother, H.qW, H.qeid,
-                         tkey, tval, tmask, tbits);
+        scan_entries<WT>(a, o, tid, BS, tot, H.mark, gshift, H.soff, H.sq, H.qcur, H.qlim,
+                         H.qother, H.qW, H.qeid, tkey, tval, tmask, tbits);
         probes += tid == 0 ? (unsigned long long)tot : 0ull;
         __syncthreads();
         if (tid < nq) H.qcur[tid] += c;
@@ -912,7 +1043,7 @@ __global__ __launch_bounds__(LT_BS) void k_tb_light(TbArgs a) {
   const int gw = (blockIdx.x * LT_BS + threadIdx.x) / WAVE;
   const int nw = gridDim.x * (LT_BS / WAVE);
   unsigned long long probes = 0;
-  const int nlight = a.tickets[5];
+  const int nlight = a.tickets[TK_LIGHT];
   for (int j = gw; j < nlight; j += nw) {
     {
       const int i = a.llist[j];
@@ -944,17 +1075,26 @@ __global__ __launch_bounds__(LT_BS) void k_tb_light(TbArgs a) {
         wave_sync();
         for (int D = Q_D0;; D = min(2 * D, Q_DMAX)) {
           const int c = lane < nq ? max(0, min(D, L.qlim[lane] - mycur)) : 0;
-          const int incl = wave_incl_scan(c);
-          const int tot = __shfl(incl, WAVE - 1, WAVE);
+          const int incl = wave_incl_scan(live_pack(c));
+          const int packed = __shfl(incl, WAVE - 1, WAVE);
+          const int tot = packed & ((1 << LIVE_SH) - 1);
           if (tot == 0) break;
-          if (lane < nq) {
-            L.qoff[lane] = incl - c;
-            L.qcur[lane] = mycur;
+          const int gshift = mark_shift(tot, LT_MARKS, D);
+          if (lane < nq) L.qcur[lane] = mycur;
+          if (c > 0) {
+            const int run = incl - live_pack(c);
+            const int sl = run >> LIVE_SH, off = run & ((1 << LIVE_SH) - 1);
+            L.sq[sl] = lane;
+            L.soff[sl] = off;
+            put_marks(L.mark, gshift, sl, off, c);
           }
-          if (lane == 0) L.qoff[nq] = tot;
+          if (lane == 0) {
+            L.soff[packed >> LIVE_SH] = tot;
+            L.mark[((tot - 1) >> gshift) + 1] = (packed >> LIVE_SH) - 1;
+          }
           wave_sync();
-          scan_entries<WT>(a, o, lane, WAVE, tot, nq, L.qoff, L.qcur, L.qlim, L.qother, L.qW,
-                           L.qeid, L.key, L.val, tmask, tbits);
+          scan_entries<WT>(a, o, lane, WAVE, tot, L.mark, gshift, L.soff, L.sq, L.qcur, L.qlim,
+                           L.qother, L.qW, L.qeid, L.key, L.val, tmask, tbits);
           probes += lane == 0 ? (unsigned long long)tot : 0ull;
           wave_sync();
           mycur += c;
@@ -1002,16 +1142,10 @@ __global__ void k_compact(const int32_t *row_ptr, const int32_t *col, const uint
 // ------------------------------------------------------------ host side
 namespace {
 struct PruneLayout {
-  int rep;
-  size_t src, cnt, cptr, cb, rank, cyw, ceid, rs, sl, llist, work, hflag, hl[3][6], gsz,
+  int cs, nb, ct, tiles;
+  size_t src, btot, bfill, bstart, stage, ccnt, cfill, cb, cyw, ceid, rs, sl, llist, work, hflag, hl[NTIER][6], gsz,
       goff, gkey, gval, tmp, misc, pos, total;
 };
-
-int replicas(int n) {
-  if ((long long)n * 16 <= (1ll << 26)) return 16;
-  if ((long long)n * 4 <= (1ll << 28)) return 4;
-  return 1;
-}
 
 PruneLayout prune_layout(int n, int m, bool compact) {
   PruneLayout L;
@@ -1021,17 +1155,25 @@ PruneLayout prune_layout(int n, int m, bool compact) {
     off += align_up(x ? x : 1, 256);
     return at;
   };
-  L.rep = replicas(n);
+  L.cs = 0;
+  while (n > 0 && ((n - 1) >> L.cs) + 1 > CB_MAX) L.cs++;
+  L.nb = n > 0 ? ((n - 1) >> L.cs) + 1 : 1;
+  // tiles of whole multiples of the workgroup, at most C_TILES of them
+  const long long per = ((long long)m + C_TILES - 1) / C_TILES;
+  L.ct = (int)((per + C_BS - 1) / C_BS * C_BS);
+  if (L.ct < 8 * C_BS) L.ct = 8 * C_BS;
+  L.tiles = m > 0 ? (int)(((long long)m + L.ct - 1) / L.ct) : 0;
   const size_t n2 = 2ull * n;
-  const size_t nr = (size_t)n * L.rep;
   // the global tables hold at most 2 slots per list entry, rounded up to a
   // power of two: below 8 m slots over all in- and out-lists
   const size_t gslots = 8ull * (size_t)m + G_UNIT;
   L.src = take(4ull * m);
-  L.cnt = take(4 * nr);
-  L.cptr = take(4 * (nr + 1));
+  L.btot = take(4 * (size_t)L.nb);
+  L.bfill = take(4 * (size_t)L.nb);
+  L.bstart = take(4 * ((size_t)L.nb + 1));
+  L.ccnt = take(4 * (size_t)n);
+  L.cfill = take(4 * (size_t)n);
   L.cb = take(4 * ((size_t)n + 1));
-  L.rank = take(4ull * m);
   L.cyw = take(8ull * m);
   L.ceid = take(4ull * m);
   L.rs = take(8ull * m);
@@ -1039,7 +1181,7 @@ PruneLayout prune_layout(int n, int m, bool compact) {
   L.llist = take(4 * n2);
   L.work = take(4 * n2);
   L.hflag = take(4 * n2);
-  for (int t = 0; t < 3; t++) {
+  for (int t = 0; t < NTIER; t++) {
     L.hl[t][0] = take(4 * n2);                           // flag
     L.hl[t][1] = take(4 * (n2 + 1));                     // pos
     L.hl[t][2] = take(4 * n2);                           // id
@@ -1052,8 +1194,9 @@ PruneLayout prune_layout(int n, int m, bool compact) {
   L.gsz = take(4 * n2);
   L.goff = take(4 * (n2 + 1));
   L.gkey = take(4 * gslots);
+  L.stage = L.gkey;  // 16 m bytes, dead before the global tables are cleared
   L.gval = take(4 * gslots);
-  const size_t scan_n = nr > n2 + 1 ? nr : n2 + 1;
+  const size_t scan_n = n2 + 1;
   L.tmp = take(scan_tmp_bytes((int)(scan_n > (size_t)m + 1 ? scan_n : (size_t)m + 1)));
   L.misc = take(256);
   L.pos = compact ? take(4ull * (m + 1)) : 0;
@@ -1072,9 +1215,12 @@ void launch_resident(K kernel, int bs, int grid_cus, const TbArgs &a, hipStream_
 template <int WT>
 void launch_scan_kernels(const TbArgs &a, int grid_cus, hipStream_t st) {
   launch_resident(k_tb_light<WT>, LT_BS, grid_cus, a, st);
-  launch_resident(k_tb_heavy<WT, 0, HM_BS, HS_SLOTS, HM_Q>, HM_BS, grid_cus, a, st);
-  launch_resident(k_tb_heavy<WT, 1, HM_BS, HM_SLOTS, HM_Q>, HM_BS, grid_cus, a, st);
-  launch_resident(k_tb_heavy<WT, 2, TB_BS, HV_SLOTS, HV_Q>, TB_BS, grid_cus, a, st);
+  static_assert(NTIER == 4, "one launch per heavy tier");
+  launch_resident(k_tb_heavy<WT, 0, HM_BS, HS_SLOTS, HM_Q, HM_MARKS>, HM_BS, grid_cus, a, st);
+  launch_resident(k_tb_heavy<WT, 1, HM_BS, HM1_SLOTS, HM_Q, HM_MARKS>, HM_BS, grid_cus, a, st);
+  launch_resident(k_tb_heavy<WT, 2, HM_BS, HM_SLOTS, HM_Q, HM_MARKS>, HM_BS, grid_cus, a, st);
+  launch_resident(k_tb_heavy<WT, T_BIG, TB_BS, HV_SLOTS, HV_Q, HV_MARKS>, TB_BS, grid_cus, a,
+                  st);
 }
 
 size_t prune_ws_bytes(int n, int m, bool compact) { return prune_layout(n, m, compact).total; }
@@ -1094,12 +1240,17 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   a.local = local;
   a.bsize = bsize;
   a.keep = keep;
-  a.rep = L.rep;
+  a.cs = L.cs;
+  a.nb = L.nb;
+  a.ct = L.ct;
   a.src = reinterpret_cast<int32_t *>(ws + L.src);
-  a.cnt = reinterpret_cast<int32_t *>(ws + L.cnt);
-  a.cptr = reinterpret_cast<int32_t *>(ws + L.cptr);
+  a.btot = reinterpret_cast<int32_t *>(ws + L.btot);
+  a.bfill = reinterpret_cast<int32_t *>(ws + L.bfill);
+  a.bstart = reinterpret_cast<int32_t *>(ws + L.bstart);
+  a.stage = reinterpret_cast<int4 *>(ws + L.stage);
+  a.ccnt = reinterpret_cast<int32_t *>(ws + L.ccnt);
+  a.cfill = reinterpret_cast<int32_t *>(ws + L.cfill);
   a.cb = reinterpret_cast<int32_t *>(ws + L.cb);
-  a.rank = reinterpret_cast<int32_t *>(ws + L.rank);
   a.cyw = reinterpret_cast<int2 *>(ws + L.cyw);
   a.ceid = reinterpret_cast<int32_t *>(ws + L.ceid);
   a.rs = reinterpret_cast<int2 *>(ws + L.rs);
@@ -1107,7 +1258,7 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   a.llist = reinterpret_cast<int32_t *>(ws + L.llist);
   a.work = reinterpret_cast<int32_t *>(ws + L.work);
   a.hflag = reinterpret_cast<int32_t *>(ws + L.hflag);
-  for (int t = 0; t < 3; t++) {
+  for (int t = 0; t < NTIER; t++) {
     HList &h = a.hl[t];
     h.flag = reinterpret_cast<int32_t *>(ws + L.hl[t][0]);
     h.pos = reinterpret_cast<int32_t *>(ws + L.hl[t][1]);
@@ -1133,21 +1284,26 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   if (validate && launch_validate(g, 1, 0, a.status, st) != hipSuccess) return SSSP_ERR_HIP;
   hipLaunchKernelGGL(k_tb_zero, dim3(blocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_tb_tails, dim3(blocks), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(k_tb_indeg, dim3(blocks), dim3(256), 0, st, a);
-  if (launch_excl_scan(a.cnt, n * L.rep, a.cptr, tmp, st) != hipSuccess) return SSSP_ERR_HIP;
-  hipLaunchKernelGGL(k_tb_cols, dim3(blocks), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(k_tb_fill, dim3(blocks), dim3(256), 0, st, a);
+  const int chunks = (int)(((long long)m + CCH - 1) / CCH);
+  if (m > 0) {
+    hipLaunchKernelGGL(k_csc_hist, dim3(L.tiles), dim3(C_BS), 0, st, a);
+    if (launch_excl_scan(a.btot, L.nb, a.bstart, tmp, st) != hipSuccess) return SSSP_ERR_HIP;
+    hipLaunchKernelGGL(k_csc_scatter, dim3(L.tiles), dim3(C_BS), 0, st, a);
+    hipLaunchKernelGGL(k_csc_count, dim3(chunks), dim3(C_BS), 0, st, a);
+  }
+  if (launch_excl_scan(a.ccnt, n, a.cb, tmp, st) != hipSuccess) return SSSP_ERR_HIP;
+  if (m > 0) hipLaunchKernelGGL(k_csc_place, dim3(chunks), dim3(C_BS), 0, st, a);
   hipLaunchKernelGGL(k_tb_sort_class, dim3(grid_cus), dim3(CLS_BS), 0, st, a);
   hipLaunchKernelGGL(k_tb_sort_small, dim3(blocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_tb_sort_mid, dim3(grid_cus * 8), dim3(SORT_BS), 0, st, a);
   hipLaunchKernelGGL(k_tb_work, dim3(blocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_tb_classify, dim3(grid_cus * 2), dim3(CLF_BS), 0, st, a);
-  for (int t = 0; t < 3; t++)
+  for (int t = 0; t < NTIER; t++)
     if (launch_excl_scan(a.hl[t].flag, 2 * n, a.hl[t].pos, tmp, st) != hipSuccess)
       return SSSP_ERR_HIP;
   if (launch_excl_scan(a.gsz, 2 * n, a.goff, tmp, st) != hipSuccess) return SSSP_ERR_HIP;
   hipLaunchKernelGGL(k_tb_heavy_list, dim3(blocks), dim3(256), 0, st, a);
-  for (int t = 0; t < 3; t++)
+  for (int t = 0; t < NTIER; t++)
     if (launch_excl_scan(a.hl[t].items, 2 * n, a.hl[t].off, tmp, st) != hipSuccess)
       return SSSP_ERR_HIP;
   hipLaunchKernelGGL(k_tb_item_map, dim3(blocks), dim3(256), 0, st, a);
