@@ -70,7 +70,6 @@ constexpr int ITEM_MINQ = 32;        // an item covers at least this many arcs
 constexpr int HV_TARGET = 1 << 18;   // heavy: estimated probes per item
 constexpr int SORT_MIN = 16;         // lists of SORT_MIN+1 .. SORT_MAX entries
 constexpr int SORT_MAX = 4096;       //   are sorted by cost
-constexpr int SORT_BS = 256;
 constexpr int SORT_WAVE = 4 * 64;    // longest list sorted by one wave
 constexpr int Q_D0 = 16;             // first scan chunk of an arc
 constexpr int Q_DMAX = 1024;         // chunk cap
@@ -116,6 +115,7 @@ struct TbArgs {
   int2 *cyw;        // m: CSC entries (tail, cost); sorted lists by cost
   int32_t *ceid;    // m: CSC -> CSR edge id (moves with cyw)
   int2 *rs;         // m: CSR rows as (head, cost); sorted lists by cost
+  int2 *lmeta;      // 2n: (least cost, bucket shift) of an ordered list; shift -1: unordered
   int32_t *sl;      // 2n: lists to sort, short ones from the front, long
                     //     ones (> SORT_WAVE entries) from the back
   int32_t *work;    // 2n: probes of owner i (i < n: in-table of i; else out-table of i-n)
@@ -346,12 +346,27 @@ __global__ __launch_bounds__(C_BS) void k_csc_place(TbArgs a) {
     if (s_w[c]) atomicAdd(&a.work[x0 + c], s_w[c]);
 }
 
-// ------------------------------------------------------------------ sort
+// ------------------------------------------------------------------ order
 // List i < n is CSR row i (entries in rs), list n + x is CSC column x
-// (entries in cyw, with ceid carried along).  Sort keys are
-// cost << 32 | vertex: costs are uint32 or the bits of nonnegative floats,
-// which order the same way.
+// (entries in cyw, with ceid carried along).  Every list of SORT_MIN+1 ..
+// SORT_MAX entries is put in cost order by a counting sort over NBK
+// buckets of width 2^s above its least cost lo, s the least shift that
+// fits its cost span: an exact cost order when the span is below NBK (any
+// integer costs up to 255 apart), bucket order otherwise.  Costs compare
+// as uint32 bits (nonnegative floats order the same way).  lmeta keeps
+// (lo, s) per ordered list for the scans' stop rule; the order of equal
+// buckets is arbitrary.
+constexpr int NBK = 256;
+constexpr int ORD_BS = 256;          // workgroup of a long list (one bucket per thread)
+constexpr int ORD_R = SORT_MAX / ORD_BS;
+
 __device__ __forceinline__ bool sorted_len(int len) { return len > SORT_MIN && len <= SORT_MAX; }
+
+__device__ __forceinline__ int bucket_shift(uint32_t span) {
+  int s = 0;
+  while ((span >> s) >= (uint32_t)NBK) s++;
+  return s;
+}
 
 struct SortSeg {
   int beg, len;
@@ -371,16 +386,14 @@ __device__ __forceinline__ SortSeg sort_seg(const TbArgs &a, int i) {
   return g;
 }
 
-__device__ __forceinline__ unsigned long long sort_key(const TbArgs &a, const SortSeg &g, int p,
-                                                       int &pay) {
-  const int2 yw = g.row ? a.rs[p] : a.cyw[p];
+__device__ __forceinline__ void ord_get(const TbArgs &a, const SortSeg &g, int p, int2 &yw,
+                                        int &pay) {
+  yw = g.row ? a.rs[p] : a.cyw[p];
   pay = g.row ? 0 : a.ceid[p];
-  return ((unsigned long long)(uint32_t)yw.y << 32) | (uint32_t)yw.x;
 }
 
-__device__ __forceinline__ void sort_put(const TbArgs &a, const SortSeg &g, int p,
-                                         unsigned long long k, int pay) {
-  const int2 yw = make_int2((int)(uint32_t)k, (int)(uint32_t)(k >> 32));
+__device__ __forceinline__ void ord_put(const TbArgs &a, const SortSeg &g, int p, int2 yw,
+                                        int pay) {
   if (g.row) {
     a.rs[p] = yw;
   } else {
@@ -389,7 +402,17 @@ __device__ __forceinline__ void sort_put(const TbArgs &a, const SortSeg &g, int 
   }
 }
 
-// Thread per list: queue the lists to sort (two atomics per workgroup pass).
+template <typename T>
+__device__ __forceinline__ T wave_max(T x) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const T y = __shfl_xor(x, o, WAVE);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+// Thread per list: queue the lists to order (two atomics per workgroup pass).
 constexpr int CLS_BS = 1024;
 __global__ __launch_bounds__(CLS_BS) void k_tb_sort_class(TbArgs a) {
   __shared__ int s_cnt[2][CLS_BS / WAVE];
@@ -424,153 +447,136 @@ __global__ __launch_bounds__(CLS_BS) void k_tb_sort_class(TbArgs a) {
     const unsigned long long below = (1ull << lane) - 1ull;
     if (srt && !longl) a.sl[offs + __popcll(bs & below)] = i;
     if (longl) a.sl[n2 - 1 - (offl + __popcll(bl & below))] = i;
+    if (i < n2) a.lmeta[i] = make_int2(0, -1);  // unordered unless ordered below
     __syncthreads();
   }
 }
 
-__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int j) {
-  const int lo = __shfl_xor((int)(uint32_t)v, j, WAVE);
-  const int hi = __shfl_xor((int)(uint32_t)(v >> 32), j, WAVE);
-  return ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo;
-}
-
-// Bitonic sorting network over 64*R keys (with payloads) held by the wave,
-// element e = lane + 64*r in k[r]; ascending in e.
+// One wave per short queued list (SORT_MIN < length <= SORT_WAVE): the
+// entries stay in registers, the bucket counters in the wave's LDS.
 template <int R>
-__device__ __forceinline__ void wave_sort(unsigned long long (&k)[R], int (&p)[R]) {
+__device__ __forceinline__ void wave_order(const TbArgs &a, int li, const SortSeg &g, int *cnt) {
   const int lane = lane_id();
+  int2 yw[R];
+  int pay[R], bk[R], rk[R];
+  uint32_t lo = 0xFFFFFFFFu, hi = 0u;
 #pragma unroll
-  for (int size = 2; size <= WAVE * R; size <<= 1)
-#pragma unroll
-    for (int j = size >> 1; j > 0; j >>= 1) {
-      if (j >= WAVE) {  // both elements of a pair are in this lane
-        const int jr = j / WAVE;
-#pragma unroll
-        for (int r = 0; r < R; r++) {
-          if (r & jr) continue;
-          const int r2 = r | jr;
-          const bool asc = ((lane + WAVE * r) & size) == 0;
-          if (asc ? k[r2] < k[r] : k[r] < k[r2]) {
-            const unsigned long long tk = k[r];
-            k[r] = k[r2];
-            k[r2] = tk;
-            const int tp = p[r];
-            p[r] = p[r2];
-            p[r2] = tp;
-          }
-        }
-      } else {
-#pragma unroll
-        for (int r = 0; r < R; r++) {
-          const int e = lane + WAVE * r;
-          const unsigned long long o = shfl_xor_u64(k[r], j);
-          const int op = __shfl_xor(p[r], j, WAVE);
-          const bool take_min = ((e & j) == 0) == ((e & size) == 0);
-          if (take_min ? o < k[r] : k[r] < o) {
-            k[r] = o;
-            p[r] = op;
-          }
-        }
-      }
+  for (int r = 0; r < R; r++) {
+    const int e = lane + WAVE * r;
+    pay[r] = 0;
+    yw[r] = make_int2(0, 0);
+    if (e < g.len) {
+      ord_get(a, g, g.beg + e, yw[r], pay[r]);
+      lo = min(lo, (uint32_t)yw[r].y);
+      hi = max(hi, (uint32_t)yw[r].y);
     }
+  }
+  lo = wave_min(lo);
+  hi = wave_max(hi);
+  const int s = bucket_shift(hi - lo);
+  for (int b = lane; b < NBK; b += WAVE) cnt[b] = 0;
+  wave_sync();
+#pragma unroll
+  for (int r = 0; r < R; r++)
+    if (lane + WAVE * r < g.len) {
+      bk[r] = (int)(((uint32_t)yw[r].y - lo) >> s);
+      rk[r] = atomicAdd(&cnt[bk[r]], 1);
+    }
+  wave_sync();
+  // exclusive scan of the NBK counters, NBK / WAVE consecutive ones per lane
+  constexpr int PL = NBK / WAVE;
+  int c[PL], sum = 0;
+#pragma unroll
+  for (int k = 0; k < PL; k++) {
+    c[k] = cnt[lane * PL + k];
+    sum += c[k];
+  }
+  int off = wave_incl_scan(sum) - sum;
+#pragma unroll
+  for (int k = 0; k < PL; k++) {
+    cnt[lane * PL + k] = off;
+    off += c[k];
+  }
+  wave_sync();
+#pragma unroll
+  for (int r = 0; r < R; r++)
+    if (lane + WAVE * r < g.len) ord_put(a, g, g.beg + cnt[bk[r]] + rk[r], yw[r], pay[r]);
+  if (lane == 0) a.lmeta[li] = make_int2((int)lo, s);
+  wave_sync();
 }
 
-template <int R>
-__device__ __forceinline__ void wave_sort_list(const TbArgs &a, const SortSeg &g) {
-  const int lane = lane_id();
-  unsigned long long k[R];
-  int p[R];
-#pragma unroll
-  for (int r = 0; r < R; r++) {
-    const int e = lane + WAVE * r;
-    p[r] = 0;
-    k[r] = e < g.len ? sort_key(a, g, g.beg + e, p[r]) : ~0ull;
-  }
-  wave_sort<R>(k, p);
-#pragma unroll
-  for (int r = 0; r < R; r++) {
-    const int e = lane + WAVE * r;
-    if (e < g.len) sort_put(a, g, g.beg + e, k[r], p[r]);
-  }
-}
-
-// One wave per short queued list (SORT_MIN < length <= SORT_WAVE), sorted
-// in registers.
-__global__ void k_tb_sort_small(TbArgs a) {
+__global__ __launch_bounds__(256) void k_tb_sort_small(TbArgs a) {
+  __shared__ int s_cnt[256 / WAVE][NBK];
   if (*a.status) return;
+  int *cnt = s_cnt[threadIdx.x / WAVE];
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int nwaves = gridDim.x * blockDim.x / WAVE;
   const int ns = a.tickets[TK_SORT_SHORT];
   for (int j = wave; j < ns; j += nwaves) {
-    const SortSeg g = sort_seg(a, a.sl[j]);
-    if (g.len <= WAVE) wave_sort_list<1>(a, g);
-    else if (g.len <= 2 * WAVE) wave_sort_list<2>(a, g);
-    else wave_sort_list<4>(a, g);
+    const int li = a.sl[j];
+    const SortSeg g = sort_seg(a, li);
+    if (g.len <= WAVE) wave_order<1>(a, li, g, cnt);
+    else if (g.len <= 2 * WAVE) wave_order<2>(a, li, g, cnt);
+    else wave_order<4>(a, li, g, cnt);
   }
 }
 
 // One workgroup per long queued list (SORT_WAVE < length <= SORT_MAX):
-// bitonic sort in LDS, padded to a power of two.  A stage with pair
-// distance <= 64 keeps every wave inside its own 128-key blocks, so two such
-// stages in a row need only a wave barrier.
-__global__ __launch_bounds__(SORT_BS) void k_tb_sort_mid(TbArgs a) {
-  __shared__ unsigned long long sk[SORT_MAX];
-  __shared__ int sp[SORT_MAX];
+// ORD_R entries per thread in registers, one bucket counter per thread.
+__global__ __launch_bounds__(ORD_BS) void k_tb_sort_mid(TbArgs a) {
+  static_assert(ORD_BS == NBK, "one bucket per thread");
+  __shared__ int s_cnt[NBK];
+  __shared__ uint32_t s_lo[ORD_BS / WAVE], s_hi[ORD_BS / WAVE];
+  __shared__ int s_ws[ORD_BS / WAVE + 1];
   if (*a.status) return;
   const int tid = threadIdx.x;
   const int nl = a.tickets[TK_SORT_LONG];
   for (int j = blockIdx.x; j < nl; j += gridDim.x) {
-    const SortSeg g = sort_seg(a, a.sl[2 * a.n - 1 - j]);
-    int N = 2 * SORT_WAVE;
-    while (N < g.len) N <<= 1;
-    for (int p = tid; p < N; p += SORT_BS) {
-      int pay = 0;
-      sk[p] = p < g.len ? sort_key(a, g, g.beg + p, pay) : ~0ull;
-      sp[p] = pay;
-    }
-    __syncthreads();
-    // the stages up to size SORT_WAVE in registers: each wave sorts whole
-    // SORT_WAVE-key chunks and stores them ascending or descending, as the
-    // network would leave them
-    for (int c = tid / WAVE; c < N / SORT_WAVE; c += SORT_BS / WAVE) {
-      unsigned long long k[SORT_WAVE / WAVE];
-      int pv[SORT_WAVE / WAVE];
-      const int lane = lane_id();
+    const int li = a.sl[2 * a.n - 1 - j];
+    const SortSeg g = sort_seg(a, li);
+    int2 yw[ORD_R];
+    int pay[ORD_R], bk[ORD_R], rk[ORD_R];
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
 #pragma unroll
-      for (int r = 0; r < SORT_WAVE / WAVE; r++) {
-        k[r] = sk[c * SORT_WAVE + lane + WAVE * r];
-        pv[r] = sp[c * SORT_WAVE + lane + WAVE * r];
-      }
-      wave_sort<SORT_WAVE / WAVE>(k, pv);
-      const bool asc = ((c * SORT_WAVE) & SORT_WAVE) == 0;
-#pragma unroll
-      for (int r = 0; r < SORT_WAVE / WAVE; r++) {
-        const int e = lane + WAVE * r;
-        const int dst = c * SORT_WAVE + (asc ? e : SORT_WAVE - 1 - e);
-        sk[dst] = k[r];
-        sp[dst] = pv[r];
+    for (int r = 0; r < ORD_R; r++) {
+      const int e = tid + ORD_BS * r;
+      pay[r] = 0;
+      yw[r] = make_int2(0, 0);
+      if (e < g.len) {
+        ord_get(a, g, g.beg + e, yw[r], pay[r]);
+        lo = min(lo, (uint32_t)yw[r].y);
+        hi = max(hi, (uint32_t)yw[r].y);
       }
     }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    if (lane_id() == 0) {
+      s_lo[tid / WAVE] = lo;
+      s_hi[tid / WAVE] = hi;
+    }
+    s_cnt[tid] = 0;
     __syncthreads();
-    for (int size = 2 * SORT_WAVE; size <= N; size <<= 1)
-      for (int jj = size >> 1; jj > 0; jj >>= 1) {
-        for (int i = tid; i < N / 2; i += SORT_BS) {
-          const int lo = 2 * i - (i & (jj - 1));
-          const int hi = lo + jj;
-          const unsigned long long x = sk[lo], y = sk[hi];
-          if ((x > y) == ((lo & size) == 0)) {
-            sk[lo] = y;
-            sk[hi] = x;
-            const int t = sp[lo];
-            sp[lo] = sp[hi];
-            sp[hi] = t;
-          }
-        }
-        const int next = jj > 1 ? jj >> 1 : size;  // pair distance of the next stage
-        if (jj <= WAVE && next <= WAVE) wave_sync();
-        else __syncthreads();
+#pragma unroll
+    for (int w = 0; w < ORD_BS / WAVE; w++) {
+      lo = min(lo, s_lo[w]);
+      hi = max(hi, s_hi[w]);
+    }
+    const int s = bucket_shift(hi - lo);
+#pragma unroll
+    for (int r = 0; r < ORD_R; r++)
+      if (tid + ORD_BS * r < g.len) {
+        bk[r] = (int)(((uint32_t)yw[r].y - lo) >> s);
+        rk[r] = atomicAdd(&s_cnt[bk[r]], 1);
       }
-    for (int p = tid; p < g.len; p += SORT_BS) sort_put(a, g, g.beg + p, sk[p], sp[p]);
+    __syncthreads();
+    int tot;
+    const int off = block_excl_scan<ORD_BS>(s_cnt[tid], s_ws, &tot);
+    s_cnt[tid] = off;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ORD_R; r++)
+      if (tid + ORD_BS * r < g.len) ord_put(a, g, g.beg + s_cnt[bk[r]] + rk[r], yw[r], pay[r]);
+    if (tid == 0) a.lmeta[li] = make_int2((int)lo, s);
     __syncthreads();
   }
 }
@@ -769,9 +775,29 @@ __device__ __forceinline__ int list_key(const TbArgs &a, const Owner &o, int p, 
 // W, its id and its other end.
 struct Query {
   int beg, len;
-  uint32_t W;
+  uint32_t W, stop;  // stop: entries of higher cost end the scan
   int eid, other;
 };
+
+// Stop bound of a scan of a list with metadata lm (its lmeta entry) for an
+// arc of cost W.  Only entries of
+// cost <= W - 1 (as uint32 bits: the next lower float for fp32) can be the
+// cheap half of a detour; in an ordered list every entry after one in a
+// higher bucket than W - 1's costs more, so an entry of cost above the last
+// cost of that bucket ends the scan.  Unordered lists never stop; a list
+// whose least cost is >= W is not scanned at all (len = 0).
+__device__ __forceinline__ uint32_t scan_stop(int2 lm, uint32_t W, int &len) {
+  if (len == 0 || lm.y < 0) return 0xFFFFFFFFu;
+  const uint32_t lo = (uint32_t)lm.x;
+  if (W <= lo) {
+    len = 0;
+    return 0u;
+  }
+  const unsigned long long last =
+      (unsigned long long)lo + (((unsigned long long)(((W - 1u) - lo) >> lm.y) + 1ull) << lm.y) -
+      1ull;
+  return last >= 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)last;
+}
 
 __device__ __forceinline__ Query make_query(const TbArgs &a, const Owner &o, int p) {
   Query q;
@@ -779,19 +805,23 @@ __device__ __forceinline__ Query make_query(const TbArgs &a, const Owner &o, int
     const int2 uw = a.cyw[p];
     const int u = uw.x;
     const int rs = a.row_ptr[u], ou = a.row_ptr[u + 1] - rs;
+    const int2 lm = a.lmeta[u];  // loaded with the row bounds, not after them
     q.beg = rs;
     q.len = ou <= o.llen ? ou : 0;
     q.W = (uint32_t)uw.y;
     q.eid = a.ceid[p];
     q.other = u;
+    q.stop = scan_stop(lm, q.W, q.len);
   } else {  // arc (u = t -> x): scan N_in(x) when |N_in(x)| < |N_out(u)|
     const int x = a.col[p];
     const int cs = cbeg(a, x), ix = clen(a, x);
+    const int2 lm = a.lmeta[a.n + x];
     q.beg = cs;
     q.len = o.llen <= ix ? 0 : ix;
     q.W = a.w[p];
     q.eid = p;
     q.other = x;
+    q.stop = scan_stop(lm, q.W, q.len);
   }
   return q;
 }
@@ -803,11 +833,12 @@ __device__ __forceinline__ Query make_query(const TbArgs &a, const Owner &o, int
 constexpr int STEP_STOP = 1, STEP_HIT = 2;
 template <int WT>
 __device__ __forceinline__ int tb_check(const TbArgs &a, const Owner &o, int2 yw, int other,
-                                        bool sorted, uint32_t W, int eid, const int32_t *tkey,
+                                        uint32_t stop, uint32_t W, int eid, const int32_t *tkey,
                                         const uint32_t *tval, int tmask, int tbits) {
   const int y = yw.x;
   const uint32_t wa = (uint32_t)yw.y;
-  if (sorted && wa >= W) return STEP_STOP;
+  if (wa > stop) return STEP_STOP;
+  if (wa >= W) return 0;  // w1 >= W: no detour through this entry
   const int u = o.mode == 0 ? other : o.t;
   const int x = o.mode == 0 ? o.t : other;
   if (y == u || y == x) return 0;
@@ -867,7 +898,6 @@ __device__ __forceinline__ void lower_lim(int32_t *p, int step, int f) {
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-constexpr int32_t UNSORTED = (int32_t)0x80000000;  // flag bit in qother
 constexpr int SCAN_U = 4;  // scanned entries loaded ahead per lane
 
 // Examines the flattened entries idx = first, first+step, ... < tot of the
@@ -877,7 +907,8 @@ __device__ __forceinline__ void scan_entries(const TbArgs &a, const Owner &o, in
                                              int step, int tot, const int32_t *mark, int gshift,
                                              const int32_t *soff, const int32_t *sq,
                                              const int32_t *qcur, int32_t *qlim,
-                                             const int32_t *qother, const uint32_t *qW,
+                                             const int32_t *qother, const uint32_t *qstop,
+                                             const uint32_t *qW,
                                              const int32_t *qeid, const int32_t *tkey,
                                              const uint32_t *tval, int tmask, int tbits) {
   const int2 *list = o.mode == 0 ? a.rs : a.cyw;
@@ -902,8 +933,7 @@ __device__ __forceinline__ void scan_entries(const TbArgs &a, const Owner &o, in
 #pragma unroll
     for (int u = 0; u < SCAN_U; u++) {
       if (f[u] < 0 || f[u] >= ld_lim(&qlim[q[u]])) continue;
-      const int oth = qother[q[u]];
-      lower_lim(&qlim[q[u]], tb_check<WT>(a, o, yw[u], oth & 0x7FFFFFFF, oth >= 0, qW[q[u]],
+      lower_lim(&qlim[q[u]], tb_check<WT>(a, o, yw[u], qother[q[u]], qstop[q[u]], qW[q[u]],
                                           qeid[q[u]], tkey, tval, tmask, tbits), f[u]);
     }
   }
@@ -919,7 +949,8 @@ struct TbHeavy {
   int32_t mark[NM + 1];  //   and marks
   uint32_t qW[QN];
   int32_t qeid[QN];
-  int32_t qother[QN];  // other end | UNSORTED
+  int32_t qother[QN];  // other end
+  uint32_t qstop[QN];  // stop bound
   int32_t qlim[QN];    // scan limit
 };
 constexpr int LT_MARKS = 128;
@@ -933,6 +964,7 @@ struct TbLight {         // one per wave
   uint32_t qW[WAVE];
   int32_t qeid[WAVE];
   int32_t qother[WAVE];
+  uint32_t qstop[WAVE];
   int32_t qlim[WAVE];
 };
 
@@ -998,7 +1030,8 @@ __global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
         H.qlim[tid] = q.beg + q.len;
         H.qW[tid] = q.W;
         H.qeid[tid] = q.eid;
-        H.qother[tid] = q.other | (sorted_len(q.len) ? 0 : UNSORTED);
+        H.qother[tid] = q.other;
+        H.qstop[tid] = q.stop;
       }
       __syncthreads();
       for (int D = Q_D0;; D = min(2 * D, Q_DMAX)) {
@@ -1021,7 +1054,7 @@ __global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
         }
         __syncthreads();
         scan_entries<WT>(a, o, tid, BS, tot, H.mark, gshift, H.soff, H.sq, H.qcur, H.qlim,
-                         H.qother, H.qW, H.qeid, tkey, tval, tmask, tbits);
+                         H.qother, H.qstop, H.qW, H.qeid, tkey, tval, tmask, tbits);
         probes += tid == 0 ? (unsigned long long)tot : 0ull;
         __syncthreads();
         if (tid < nq) H.qcur[tid] += c;
@@ -1070,7 +1103,8 @@ __global__ __launch_bounds__(LT_BS) void k_tb_light(TbArgs a) {
           L.qlim[lane] = q.beg + q.len;
           L.qW[lane] = q.W;
           L.qeid[lane] = q.eid;
-          L.qother[lane] = q.other | (sorted_len(q.len) ? 0 : UNSORTED);
+          L.qother[lane] = q.other;
+          L.qstop[lane] = q.stop;
         }
         wave_sync();
         for (int D = Q_D0;; D = min(2 * D, Q_DMAX)) {
@@ -1094,7 +1128,7 @@ __global__ __launch_bounds__(LT_BS) void k_tb_light(TbArgs a) {
           }
           wave_sync();
           scan_entries<WT>(a, o, lane, WAVE, tot, L.mark, gshift, L.soff, L.sq, L.qcur, L.qlim,
-                           L.qother, L.qW, L.qeid, L.key, L.val, tmask, tbits);
+                           L.qother, L.qstop, L.qW, L.qeid, L.key, L.val, tmask, tbits);
           probes += lane == 0 ? (unsigned long long)tot : 0ull;
           wave_sync();
           mycur += c;
@@ -1143,7 +1177,7 @@ __global__ void k_compact(const int32_t *row_ptr, const int32_t *col, const uint
 namespace {
 struct PruneLayout {
   int cs, nb, ct, tiles;
-  size_t src, btot, bfill, bstart, stage, ccnt, cfill, cb, cyw, ceid, rs, sl, llist, work, hflag, hl[NTIER][6], gsz,
+  size_t src, btot, bfill, bstart, stage, ccnt, cfill, cb, cyw, ceid, rs, lmeta, sl, llist, work, hflag, hl[NTIER][6], gsz,
       goff, gkey, gval, tmp, misc, pos, total;
 };
 
@@ -1177,6 +1211,7 @@ PruneLayout prune_layout(int n, int m, bool compact) {
   L.cyw = take(8ull * m);
   L.ceid = take(4ull * m);
   L.rs = take(8ull * m);
+  L.lmeta = take(8 * n2);
   L.sl = take(4 * n2);
   L.llist = take(4 * n2);
   L.work = take(4 * n2);
@@ -1254,6 +1289,7 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   a.cyw = reinterpret_cast<int2 *>(ws + L.cyw);
   a.ceid = reinterpret_cast<int32_t *>(ws + L.ceid);
   a.rs = reinterpret_cast<int2 *>(ws + L.rs);
+  a.lmeta = reinterpret_cast<int2 *>(ws + L.lmeta);
   a.sl = reinterpret_cast<int32_t *>(ws + L.sl);
   a.llist = reinterpret_cast<int32_t *>(ws + L.llist);
   a.work = reinterpret_cast<int32_t *>(ws + L.work);
@@ -1295,7 +1331,7 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   if (m > 0) hipLaunchKernelGGL(k_csc_place, dim3(chunks), dim3(C_BS), 0, st, a);
   hipLaunchKernelGGL(k_tb_sort_class, dim3(grid_cus), dim3(CLS_BS), 0, st, a);
   hipLaunchKernelGGL(k_tb_sort_small, dim3(blocks), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(k_tb_sort_mid, dim3(grid_cus * 8), dim3(SORT_BS), 0, st, a);
+  hipLaunchKernelGGL(k_tb_sort_mid, dim3(grid_cus * 8), dim3(ORD_BS), 0, st, a);
   hipLaunchKernelGGL(k_tb_work, dim3(blocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_tb_classify, dim3(grid_cus * 2), dim3(CLF_BS), 0, st, a);
   for (int t = 0; t < NTIER; t++)
