@@ -104,3 +104,39 @@ def test_pruned_solve_equals_unpruned(scale, seed):
 def test_rmat20_keep_mask_full_size():
     g = gen.rmat(20, 20)
     assert np.array_equal(gpu_keep(g, num_partitions=256), oracle.trishla(g.row_ptr, g.col, g.w))
+
+
+# Lists are put in cost order by buckets of width 2^s above their least cost;
+# the order is exact for spans below 256 and bucket order beyond.  These cases
+# reach the bucket-order stop rule (s > 0), its 32-bit overflow clamp, a
+# degenerate bucket spread, zero costs and a single cost.
+def _with_weights(g, w):
+    return gen.CSR(g.n, g.row_ptr, g.col, np.asarray(w, dtype=np.uint32))
+
+
+@pytest.mark.parametrize("wlo,whi", [(1, 1_000_000), (1, 2**32 - 1), (2**32 - 4096, 2**32 - 1)])
+def test_wide_span_u32_keep_mask(wlo, whi):
+    g = gen.rmat(13, 21, wlo=wlo, whi=whi)
+    assert np.array_equal(gpu_keep(g), oracle.trishla(g.row_ptr, g.col, g.w))
+
+
+def test_power_of_two_costs_keep_mask():
+    # costs 2^k, k uniform in 0..31: almost every entry lands in the lowest bucket
+    g = gen.rmat(13, 22)
+    k = np.random.default_rng(22).integers(0, 32, size=g.m)
+    g = _with_weights(g, np.left_shift(np.uint64(1), k.astype(np.uint64)).astype(np.uint32))
+    assert np.array_equal(gpu_keep(g), oracle.trishla(g.row_ptr, g.col, g.w))
+
+
+def test_zero_and_constant_costs_keep_mask():
+    g = gen.rmat(12, 23, wlo=0, whi=3)
+    assert np.array_equal(gpu_keep(g), oracle.trishla(g.row_ptr, g.col, g.w))
+    g = gen.rmat(12, 24, wlo=7, whi=7)
+    keep = gpu_keep(g)
+    assert keep.all() and np.array_equal(keep, oracle.trishla(g.row_ptr, g.col, g.w))
+
+
+def test_fp32_keep_mask_long_lists():
+    # scale 15 has lists of several hundred entries (the workgroup ordering)
+    g = gen.rmat(15, 25, weight="f32", wlo=0.5, whi=1.5)
+    assert np.array_equal(gpu_keep(g), oracle.trishla(g.row_ptr, g.col, g.w))
