@@ -71,11 +71,13 @@ def m_reached(g, source):
 KERNEL_SOURCES = {  # files each kernel is compiled from (for the counter-staleness check)
     "k_solve": ("internal.hpp", "solve.hip"),
     "k_tb_light": ("internal.hpp", "prune.hip"),
-    "k_tb_heavy_small": ("internal.hpp", "prune.hip"),
-    "k_tb_heavy_medium": ("internal.hpp", "prune.hip"),
+    # heavy owners by list length: <= 512, <= 1024, <= 2048 entries, and longer
+    "k_tb_heavy_t0": ("internal.hpp", "prune.hip"),
+    "k_tb_heavy_t1": ("internal.hpp", "prune.hip"),
+    "k_tb_heavy_t2": ("internal.hpp", "prune.hip"),
     "k_tb_heavy_big": ("internal.hpp", "prune.hip"),
 }
-TRISHLA_SCAN = ("k_tb_light", "k_tb_heavy_small", "k_tb_heavy_medium", "k_tb_heavy_big")
+TRISHLA_SCAN = ("k_tb_light", "k_tb_heavy_t0", "k_tb_heavy_t1", "k_tb_heavy_t2", "k_tb_heavy_big")
 
 
 def kernel_source_hash(kernel):
