@@ -89,11 +89,11 @@ template <> struct Tri<SSSP_W_F32> {
   }
 };
 
-// Heavy owners of one tier: flag (2n), its exclusive scan pos (2n+1), the
-// owners in order (id), their item counts and its exclusive scan off, and
-// the owner index of every item (map).
+// Heavy owners of one tier, in the order they were appended: the owner
+// (id), its item count and the first of its items (off), and the slot of
+// the owner of every item (map).
 struct HList {
-  int32_t *flag, *pos, *id, *items, *off, *map;
+  int32_t *id, *items, *off, *map;
 };
 
 struct TbArgs {
@@ -122,7 +122,9 @@ struct TbArgs {
   int32_t *hflag;   // 2n: 0 light or no work, else heavy tier + 1
   HList hl[NTIER];  // heavy owners per tier (T_BIG: the longest lists)
   int32_t *gsz;     // 2n: global table size in units of G_UNIT slots (0 = LDS)
-  int32_t *goff;    // 2n+1: exclusive scan of gsz
+  int32_t *goff;    // 2n: its offset (units), for owners with gsz > 0
+  int32_t *hc;      // [t] heavy owners of tier t, [NTIER + t] their items,
+                    // [2 NTIER] global table units
   int32_t *gkey;    // global tables: keys (-1 = empty)
   uint32_t *gval;   //                cheapest parallel arc
   int32_t *llist;   // 2n: light owners (order of appending)
@@ -177,6 +179,7 @@ __global__ void k_tb_status(TbArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *a.status = 0;
     for (int k = 0; k <= TK_LIGHT; k++) a.tickets[k] = 0;
+    for (int k = 0; k <= 2 * NTIER; k++) a.hc[k] = 0;
   }
   if (a.stats && blockIdx.x == 0 && threadIdx.x < (int)(sizeof(sssp_stats) / 4))
     reinterpret_cast<uint32_t *>(a.stats)[threadIdx.x] = 0u;
@@ -198,10 +201,7 @@ __global__ void k_tb_zero(TbArgs a) {
     a.btot[i] = 0;
     a.bfill[i] = 0;
   }
-  for (int i = t; i < 2 * a.n; i += stride) {
-    a.work[i] = 0;
-    for (int k = 0; k < NTIER; k++) a.hl[k].items[i] = 0;
-  }
+  for (int i = t; i < 2 * a.n; i += stride) a.work[i] = 0;
 }
 
 // One wave per row: the tail of every arc (coalesced stores only).
@@ -629,30 +629,52 @@ __device__ __forceinline__ int owner_len(const TbArgs &a, int i) {
   return a.row_ptr[u + 1] - a.row_ptr[u];
 }
 
-// Tier of every owner; light owners with work are appended to llist (one
-// atomic per workgroup pass).
+// Tier of every owner.  Light owners with work are appended to llist;
+// heavy owners to their tier's list with their items (about HV_TARGET
+// estimated probes each, at least ITEM_MINQ arcs), slots and item ranges
+// reserved with one atomic per workgroup pass and tier; an owner with a
+// global table reserves its slots.
 constexpr int CLF_BS = 1024;
 __global__ __launch_bounds__(CLF_BS) void k_tb_classify(TbArgs a) {
   __shared__ int s_cnt[CLF_BS / WAVE];
   __shared__ int s_base;
+  __shared__ int s_h[2 * NTIER];  // owners and items per tier, then their bases
   if (*a.status) return;
   const int lane = lane_id();
   const int wid = threadIdx.x / WAVE;
   const int n2 = 2 * a.n;
   for (int i0 = blockIdx.x * CLF_BS; i0 < n2; i0 += gridDim.x * CLF_BS) {
+    if (threadIdx.x < 2 * NTIER) s_h[threadIdx.x] = 0;
     const int i = i0 + threadIdx.x;
     const bool in = i < n2;
     const int wk = in ? a.work[i] : 0;
     const int len = in ? owner_len(a, i) : 0;
     const bool heavy = wk > 0 && (len > LT_DEG || wk > LT_WORK);
     const bool light = wk > 0 && !heavy;
+    const int tier = len > HM_TCAP ? T_BIG : (len > HM1_TCAP ? 2 : (len > HS_TCAP ? 1 : 0));
+    int items = 0;
+    if (heavy) {
+      const int cap = len / ITEM_MINQ > 1 ? len / ITEM_MINQ : 1;
+      const long long want = ((long long)wk + HV_TARGET - 1) / HV_TARGET;
+      items = want < 1 ? 1 : (want > cap ? cap : (int)want);
+    }
     const unsigned long long bl = __ballot(light);
     if (lane == 0) s_cnt[wid] = __popcll(bl);
     __syncthreads();
+    int jl = 0, ol = 0;
+    if (heavy) {
+      jl = atomicAdd(&s_h[tier], 1);
+      ol = atomicAdd(&s_h[NTIER + tier], items);
+    }
     if (threadIdx.x == 0) {
       int tot = 0;
       for (int w = 0; w < CLF_BS / WAVE; w++) tot += s_cnt[w];
       s_base = tot ? atomicAdd(&a.tickets[TK_LIGHT], tot) : 0;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * NTIER) {
+      const int v = s_h[threadIdx.x];
+      s_h[threadIdx.x] = v ? atomicAdd(&a.hc[threadIdx.x], v) : 0;
     }
     __syncthreads();
     int off = s_base;
@@ -660,46 +682,21 @@ __global__ __launch_bounds__(CLF_BS) void k_tb_classify(TbArgs a) {
     if (light) a.llist[off + __popcll(bl & ((1ull << lane) - 1ull))] = i;
     if (in) {
       // hflag = heavy tier + 1 (0 = light or no work)
-      const int tier = len > HM_TCAP ? T_BIG : (len > HM1_TCAP ? 2 : (len > HS_TCAP ? 1 : 0));
       a.hflag[i] = heavy ? tier + 1 : 0;
-      for (int k = 0; k < NTIER; k++) a.hl[k].flag[i] = heavy && tier == k;
       int g = 0;
       if (heavy && tier == T_BIG && len > HV_TCAP) g = (1 << tb_bits(len, 6)) / G_UNIT;
       a.gsz[i] = g;
+      if (g) a.goff[i] = atomicAdd(&a.hc[2 * NTIER], g);
+    }
+    if (heavy) {
+      const HList &h = a.hl[tier];
+      const int jj = s_h[tier] + jl, o = s_h[NTIER + tier] + ol;
+      h.id[jj] = i;
+      h.items[jj] = items;
+      h.off[jj] = o;
+      for (int k = 0; k < items; k++) h.map[o + k] = jj;
     }
     __syncthreads();
-  }
-}
-
-__global__ void k_tb_heavy_list(TbArgs a) {
-  if (*a.status) return;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int stride = gridDim.x * blockDim.x;
-  for (int i = t; i < 2 * a.n; i += stride)
-    if (a.hflag[i]) {
-      const HList &h = a.hl[a.hflag[i] - 1];
-      const int j = h.pos[i];
-      const int len = owner_len(a, i);
-      const int cap = len / ITEM_MINQ > 1 ? len / ITEM_MINQ : 1;
-      int items = (a.work[i] + HV_TARGET - 1) / HV_TARGET;
-      items = items < 1 ? 1 : (items > cap ? cap : items);
-      h.id[j] = i;
-      h.items[j] = items;
-    }
-}
-
-// Thread per heavy owner: the owner of each of its items.
-__global__ void k_tb_item_map(TbArgs a) {
-  if (*a.status) return;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int stride = gridDim.x * blockDim.x;
-  for (int tier = 0; tier < NTIER; tier++) {
-    const HList &h = a.hl[tier];
-    const int nh = h.pos[2 * a.n];
-    for (int j = t; j < nh; j += stride) {
-      const int o = h.off[j], c = h.items[j];
-      for (int k = 0; k < c; k++) h.map[o + k] = j;
-    }
   }
 }
 
@@ -708,7 +705,7 @@ __global__ void k_tb_item_map(TbArgs a) {
 // blockIdx.y over slices of each list.
 __global__ void k_tb_gclear(TbArgs a) {
   if (*a.status) return;
-  const long long total = (long long)a.goff[2 * a.n] * G_UNIT;
+  const long long total = (long long)a.hc[2 * NTIER] * G_UNIT;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long s = t; s < total; s += stride) {
@@ -720,7 +717,7 @@ __global__ void k_tb_gclear(TbArgs a) {
 __global__ __launch_bounds__(256) void k_tb_gtab(TbArgs a) {
   if (*a.status) return;
   const HList &h = a.hl[T_BIG];
-  const int nh = h.pos[2 * a.n];
+  const int nh = a.hc[T_BIG];
   for (int j = blockIdx.x; j < nh; j += gridDim.x) {
     const int i = h.id[j];
     const int g = a.gsz[i];
@@ -980,8 +977,7 @@ __global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
   if (*a.status) return;
   const int tid = threadIdx.x;
   const HList &hl = a.hl[TIER];
-  const int nh = hl.pos[2 * a.n];
-  const int total = hl.off[nh];
+  const int total = a.hc[NTIER + TIER];
   unsigned long long probes = 0;
   for (;;) {
     if (tid == 0) s_t = atomicAdd(&a.tickets[TIER], 1);
@@ -1177,7 +1173,7 @@ __global__ void k_compact(const int32_t *row_ptr, const int32_t *col, const uint
 namespace {
 struct PruneLayout {
   int cs, nb, ct, tiles;
-  size_t src, btot, bfill, bstart, stage, ccnt, cfill, cb, cyw, ceid, rs, lmeta, sl, llist, work, hflag, hl[NTIER][6], gsz,
+  size_t src, btot, bfill, bstart, stage, ccnt, cfill, cb, cyw, ceid, rs, lmeta, sl, llist, work, hflag, hl[NTIER][4], gsz,
       goff, gkey, gval, tmp, misc, pos, total;
 };
 
@@ -1217,17 +1213,15 @@ PruneLayout prune_layout(int n, int m, bool compact) {
   L.work = take(4 * n2);
   L.hflag = take(4 * n2);
   for (int t = 0; t < NTIER; t++) {
-    L.hl[t][0] = take(4 * n2);                           // flag
-    L.hl[t][1] = take(4 * (n2 + 1));                     // pos
-    L.hl[t][2] = take(4 * n2);                           // id
-    L.hl[t][3] = take(4 * n2);                           // items
-    L.hl[t][4] = take(4 * (n2 + 1));                     // off
+    L.hl[t][0] = take(4 * n2);                           // id
+    L.hl[t][1] = take(4 * n2);                           // items
+    L.hl[t][2] = take(4 * n2);                           // off
     // map: an owner has at most max(1, len / ITEM_MINQ) items and the lists
     // hold 2m entries in all
-    L.hl[t][5] = take(4 * (n2 + 2ull * (size_t)m / ITEM_MINQ + 64));
+    L.hl[t][3] = take(4 * (n2 + 2ull * (size_t)m / ITEM_MINQ + 64));
   }
   L.gsz = take(4 * n2);
-  L.goff = take(4 * (n2 + 1));
+  L.goff = take(4 * n2);
   L.gkey = take(4 * gslots);
   L.stage = L.gkey;  // 16 m bytes, dead before the global tables are cleared
   L.gval = take(4 * gslots);
@@ -1296,12 +1290,10 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   a.hflag = reinterpret_cast<int32_t *>(ws + L.hflag);
   for (int t = 0; t < NTIER; t++) {
     HList &h = a.hl[t];
-    h.flag = reinterpret_cast<int32_t *>(ws + L.hl[t][0]);
-    h.pos = reinterpret_cast<int32_t *>(ws + L.hl[t][1]);
-    h.id = reinterpret_cast<int32_t *>(ws + L.hl[t][2]);
-    h.items = reinterpret_cast<int32_t *>(ws + L.hl[t][3]);
-    h.off = reinterpret_cast<int32_t *>(ws + L.hl[t][4]);
-    h.map = reinterpret_cast<int32_t *>(ws + L.hl[t][5]);
+    h.id = reinterpret_cast<int32_t *>(ws + L.hl[t][0]);
+    h.items = reinterpret_cast<int32_t *>(ws + L.hl[t][1]);
+    h.off = reinterpret_cast<int32_t *>(ws + L.hl[t][2]);
+    h.map = reinterpret_cast<int32_t *>(ws + L.hl[t][3]);
   }
   a.gsz = reinterpret_cast<int32_t *>(ws + L.gsz);
   a.goff = reinterpret_cast<int32_t *>(ws + L.goff);
@@ -1311,6 +1303,7 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   char *misc = ws + L.misc;
   a.tickets = reinterpret_cast<int32_t *>(misc);
   a.status = reinterpret_cast<int32_t *>(misc + 128);  // after 32 ticket counters
+  a.hc = reinterpret_cast<int32_t *>(misc + 192);
   a.stats = stats;
   int32_t *pos = out_row_ptr ? reinterpret_cast<int32_t *>(ws + L.pos) : nullptr;
   *status_out = a.status;
@@ -1334,15 +1327,6 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   hipLaunchKernelGGL(k_tb_sort_mid, dim3(grid_cus * 8), dim3(ORD_BS), 0, st, a);
   hipLaunchKernelGGL(k_tb_work, dim3(blocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_tb_classify, dim3(grid_cus * 2), dim3(CLF_BS), 0, st, a);
-  for (int t = 0; t < NTIER; t++)
-    if (launch_excl_scan(a.hl[t].flag, 2 * n, a.hl[t].pos, tmp, st) != hipSuccess)
-      return SSSP_ERR_HIP;
-  if (launch_excl_scan(a.gsz, 2 * n, a.goff, tmp, st) != hipSuccess) return SSSP_ERR_HIP;
-  hipLaunchKernelGGL(k_tb_heavy_list, dim3(blocks), dim3(256), 0, st, a);
-  for (int t = 0; t < NTIER; t++)
-    if (launch_excl_scan(a.hl[t].items, 2 * n, a.hl[t].off, tmp, st) != hipSuccess)
-      return SSSP_ERR_HIP;
-  hipLaunchKernelGGL(k_tb_item_map, dim3(blocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_tb_gclear, dim3(blocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_tb_gtab, dim3(grid_cus, 16), dim3(256), 0, st, a);
   if (ev_start && hipEventRecord((hipEvent_t)ev_start, st) != hipSuccess) return SSSP_ERR_HIP;
