@@ -105,6 +105,7 @@ struct TbArgs {
   int cs, nb;       // CSC build: buckets of heads x >> cs, nb of them
   int ct;           // CSC build: arcs per tile
   int32_t *src;     // m: tail of every arc
+  int32_t *trow;    // m / TL_E + 1: row of the first arc of every tail tile
   int32_t *btot;    // nb: arcs per bucket
   int32_t *bfill;   // nb: arcs placed per bucket
   int32_t *bstart;  // nb+1: bucket offsets in stage
@@ -204,14 +205,51 @@ __global__ void k_tb_zero(TbArgs a) {
   for (int i = t; i < 2 * a.n; i += stride) a.work[i] = 0;
 }
 
-// One wave per row: the tail of every arc (coalesced stores only).
-__global__ void k_tb_tails(TbArgs a) {
+// Tail of every arc, in tiles of TL_E arcs: k_tb_tilerow records the row
+// of every tile's first arc; k_tb_tails stages the bounds of its tile's
+// rows in LDS and finds the row of each arc by a binary search there, so
+// the stores are coalesced whatever the row lengths.  A tile spanning more
+// than TL_ROWS rows (long runs of empty rows) searches row_ptr in place.
+constexpr int TL_BS = 256, TL_E = 4096, TL_ROWS = 2048;
+
+__device__ __forceinline__ int tl_tiles(const TbArgs &a) {
+  return (int)(((long long)a.m + TL_E - 1) / TL_E);
+}
+
+__global__ void k_tb_tilerow(TbArgs a) {
   if (*a.status) return;
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-  const int nwaves = gridDim.x * blockDim.x / WAVE;
-  for (int u = wave; u < a.n; u += nwaves) {
-    const int re = a.row_ptr[u + 1];
-    for (int e = a.row_ptr[u] + lane_id(); e < re; e += WAVE) a.src[e] = u;
+  const int nt = tl_tiles(a);
+  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < a.n; u += gridDim.x * blockDim.x) {
+    const int b = a.row_ptr[u], e = a.row_ptr[u + 1];
+    for (long long k = ((long long)max(b, 0) + TL_E - 1) / TL_E; k < nt && k * TL_E < e; k++)
+      a.trow[k] = u;
+  }
+}
+
+__global__ __launch_bounds__(TL_BS) void k_tb_tails(TbArgs a) {
+  __shared__ int s_rp[TL_ROWS + 1];
+  if (*a.status) return;
+  const int nt = tl_tiles(a);
+  for (int k = blockIdx.x; k < nt; k += gridDim.x) {
+    const int e0 = k * TL_E;
+    const int e1 = (int)min((long long)a.m, (long long)e0 + TL_E);
+    const int u0 = min(max(a.trow[k], 0), a.n - 1);
+    const int u1 = k + 1 < nt ? min(max(a.trow[k + 1], u0), a.n - 1) : a.n - 1;
+    const int cnt = u1 - u0 + 1;  // rows u0..u1 hold the tile's arcs
+    const bool in_lds = cnt <= TL_ROWS;
+    if (in_lds)
+      for (int r = threadIdx.x; r <= cnt; r += TL_BS) s_rp[r] = a.row_ptr[u0 + r];
+    __syncthreads();
+    for (int e = e0 + threadIdx.x; e < e1; e += TL_BS) {
+      int lo = 0, hi = cnt - 1;  // last row r with row_ptr[u0 + r] <= e
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((in_lds ? s_rp[mid] : a.row_ptr[u0 + mid]) <= e) lo = mid;
+        else hi = mid - 1;
+      }
+      a.src[e] = u0 + lo;
+    }
+    __syncthreads();
   }
 }
 
@@ -1173,7 +1211,7 @@ __global__ void k_compact(const int32_t *row_ptr, const int32_t *col, const uint
 namespace {
 struct PruneLayout {
   int cs, nb, ct, tiles;
-  size_t src, btot, bfill, bstart, stage, ccnt, cfill, cb, cyw, ceid, rs, lmeta, sl, llist, work, hflag, hl[NTIER][4], gsz,
+  size_t src, trow, btot, bfill, bstart, stage, ccnt, cfill, cb, cyw, ceid, rs, lmeta, sl, llist, work, hflag, hl[NTIER][4], gsz,
       goff, gkey, gval, tmp, misc, pos, total;
 };
 
@@ -1198,6 +1236,7 @@ PruneLayout prune_layout(int n, int m, bool compact) {
   // power of two: below 8 m slots over all in- and out-lists
   const size_t gslots = 8ull * (size_t)m + G_UNIT;
   L.src = take(4ull * m);
+  L.trow = take(4ull * ((size_t)m / TL_E + 2));
   L.btot = take(4 * (size_t)L.nb);
   L.bfill = take(4 * (size_t)L.nb);
   L.bstart = take(4 * ((size_t)L.nb + 1));
@@ -1273,6 +1312,7 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   a.nb = L.nb;
   a.ct = L.ct;
   a.src = reinterpret_cast<int32_t *>(ws + L.src);
+  a.trow = reinterpret_cast<int32_t *>(ws + L.trow);
   a.btot = reinterpret_cast<int32_t *>(ws + L.btot);
   a.bfill = reinterpret_cast<int32_t *>(ws + L.bfill);
   a.bstart = reinterpret_cast<int32_t *>(ws + L.bstart);
@@ -1312,7 +1352,10 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   hipLaunchKernelGGL(k_tb_status, dim3(1), dim3(64), 0, st, a);
   if (validate && launch_validate(g, 1, 0, a.status, st) != hipSuccess) return SSSP_ERR_HIP;
   hipLaunchKernelGGL(k_tb_zero, dim3(blocks), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(k_tb_tails, dim3(blocks), dim3(256), 0, st, a);
+  if (m > 0) {
+    hipLaunchKernelGGL(k_tb_tilerow, dim3(blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_tb_tails, dim3(blocks), dim3(TL_BS), 0, st, a);
+  }
   const int chunks = (int)(((long long)m + CCH - 1) / CCH);
   if (m > 0) {
     hipLaunchKernelGGL(k_csc_hist, dim3(L.tiles), dim3(C_BS), 0, st, a);
