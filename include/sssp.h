@@ -155,6 +155,11 @@ typedef struct {
  *   edge_map        device int32[m] or NULL: original id of kept arc i (out)
  * Kept arcs stay in their original order; the kept count is
  * out_row_ptr[n].  The out_* arrays and edge_map must be all NULL or all set.
+ * The work is ordered on `stream` as one unit.  Part of it runs on three
+ * library-owned streams of the current device, forked from `stream` and
+ * joined back with events.  Those streams and events are created on the
+ * first call and kept until the process ends.  Under stream capture
+ * everything stays on `stream`.
  */
 int sssp_prune(const sssp_csr *g, const sssp_opts *o, uint8_t *keep,
                int32_t *out_row_ptr, int32_t *out_col, void *out_w,

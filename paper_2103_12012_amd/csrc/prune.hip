@@ -36,6 +36,10 @@
 // which decides w1 + w2 < W exactly for fp32 operands (the sum is exact
 // unless one operand is below 2^-29 of the other, and then the comparison
 // with an fp32 W cannot flip).
+#include <array>
+#include <mutex>
+#include <vector>
+
 #include "internal.hpp"
 #include "launch.hpp"
 
@@ -1280,15 +1284,85 @@ void launch_resident(K kernel, int bs, int grid_cus, const TbArgs &a, hipStream_
   hipLaunchKernelGGL(kernel, dim3(grid_cus * (per_cu > 0 ? per_cu : 1)), dim3(bs), 0, st, a);
 }
 
+// Side streams and fork/join events for the concurrent scan kernels: per
+// device, created on first use (default priority, non-blocking streams)
+// and kept for the life of the process.  The mutex is held while a call
+// enqueues its fork and join, so each wait pairs with that call's record.
+constexpr int SCAN_SIDE = 3;
+struct ScanSide {
+  hipStream_t s[SCAN_SIDE] = {};
+  hipEvent_t ev[1 + SCAN_SIDE] = {};
+  bool ready = false;
+};
+
+std::mutex &scan_side_mutex() {
+  static std::mutex mu;
+  return mu;
+}
+
+// Caller holds scan_side_mutex().
+ScanSide *scan_side() {
+  static std::vector<ScanSide> per_dev;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  if ((int)per_dev.size() <= dev) per_dev.resize(dev + 1);
+  ScanSide &d = per_dev[dev];
+  if (!d.ready) {
+    for (int i = 0; i < SCAN_SIDE; i++)
+      if (!d.s[i] && hipStreamCreateWithFlags(&d.s[i], hipStreamNonBlocking) != hipSuccess) {
+        d.s[i] = nullptr;
+        return nullptr;
+      }
+    for (int i = 0; i <= SCAN_SIDE; i++)
+      if (!d.ev[i] && hipEventCreateWithFlags(&d.ev[i], hipEventDisableTiming) != hipSuccess) {
+        d.ev[i] = nullptr;
+        return nullptr;
+      }
+    d.ready = true;
+  }
+  return &d;
+}
+
+// The five scan kernels (light owners, four heavy tiers).  Each drains its
+// own ticket queue with resident workgroups, so run concurrently they fill
+// each other's tails: the tiers with the longest items go to side streams
+// forked from st and joined back with events.  Under stream capture they
+// run one after another on st.
 template <int WT>
-void launch_scan_kernels(const TbArgs &a, int grid_cus, hipStream_t st) {
-  launch_resident(k_tb_light<WT>, LT_BS, grid_cus, a, st);
+hipError_t launch_scan_kernels(const TbArgs &a, int grid_cus, hipStream_t st) {
   static_assert(NTIER == 4, "one launch per heavy tier");
-  launch_resident(k_tb_heavy<WT, 0, HM_BS, HS_SLOTS, HM_Q, HM_MARKS>, HM_BS, grid_cus, a, st);
-  launch_resident(k_tb_heavy<WT, 1, HM_BS, HM1_SLOTS, HM_Q, HM_MARKS>, HM_BS, grid_cus, a, st);
-  launch_resident(k_tb_heavy<WT, 2, HM_BS, HM_SLOTS, HM_Q, HM_MARKS>, HM_BS, grid_cus, a, st);
-  launch_resident(k_tb_heavy<WT, T_BIG, TB_BS, HV_SLOTS, HV_Q, HV_MARKS>, TB_BS, grid_cus, a,
-                  st);
+  auto k_light = k_tb_light<WT>;
+  auto k_t0 = k_tb_heavy<WT, 0, HM_BS, HS_SLOTS, HM_Q, HM_MARKS>;
+  auto k_t1 = k_tb_heavy<WT, 1, HM_BS, HM1_SLOTS, HM_Q, HM_MARKS>;
+  auto k_t2 = k_tb_heavy<WT, 2, HM_BS, HM_SLOTS, HM_Q, HM_MARKS>;
+  auto k_big = k_tb_heavy<WT, T_BIG, TB_BS, HV_SLOTS, HV_Q, HV_MARKS>;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  hipError_t err = hipStreamIsCapturing(st, &cap);
+  if (err != hipSuccess) return err;
+  if (cap != hipStreamCaptureStatusNone) {
+    launch_resident(k_light, LT_BS, grid_cus, a, st);
+    launch_resident(k_t0, HM_BS, grid_cus, a, st);
+    launch_resident(k_t1, HM_BS, grid_cus, a, st);
+    launch_resident(k_t2, HM_BS, grid_cus, a, st);
+    launch_resident(k_big, TB_BS, grid_cus, a, st);
+    return hipSuccess;
+  }
+  std::lock_guard<std::mutex> lk(scan_side_mutex());
+  ScanSide *d = scan_side();
+  if (!d) return hipErrorOutOfMemory;
+  if ((err = hipEventRecord(d->ev[0], st)) != hipSuccess) return err;
+  for (int i = 0; i < SCAN_SIDE; i++)
+    if ((err = hipStreamWaitEvent(d->s[i], d->ev[0], 0)) != hipSuccess) return err;
+  launch_resident(k_big, TB_BS, grid_cus, a, d->s[0]);
+  launch_resident(k_t2, HM_BS, grid_cus, a, d->s[1]);
+  launch_resident(k_t1, HM_BS, grid_cus, a, d->s[2]);
+  launch_resident(k_light, LT_BS, grid_cus, a, st);
+  launch_resident(k_t0, HM_BS, grid_cus, a, st);
+  for (int i = 0; i < SCAN_SIDE; i++) {
+    if ((err = hipEventRecord(d->ev[1 + i], d->s[i])) != hipSuccess) return err;
+    if ((err = hipStreamWaitEvent(st, d->ev[1 + i], 0)) != hipSuccess) return err;
+  }
+  return hipSuccess;
 }
 
 size_t prune_ws_bytes(int n, int m, bool compact) { return prune_layout(n, m, compact).total; }
@@ -1373,9 +1447,9 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   hipLaunchKernelGGL(k_tb_gclear, dim3(blocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_tb_gtab, dim3(grid_cus, 16), dim3(256), 0, st, a);
   if (ev_start && hipEventRecord((hipEvent_t)ev_start, st) != hipSuccess) return SSSP_ERR_HIP;
-  if (g.wtype == SSSP_W_U32) launch_scan_kernels<SSSP_W_U32>(a, grid_cus, st);
-  else launch_scan_kernels<SSSP_W_F32>(a, grid_cus, st);
-  if (hipGetLastError() != hipSuccess) return SSSP_ERR_HIP;
+  const hipError_t se = g.wtype == SSSP_W_U32 ? launch_scan_kernels<SSSP_W_U32>(a, grid_cus, st)
+                                              : launch_scan_kernels<SSSP_W_F32>(a, grid_cus, st);
+  if (se != hipSuccess || hipGetLastError() != hipSuccess) return SSSP_ERR_HIP;
   if (ev_stop && hipEventRecord((hipEvent_t)ev_stop, st) != hipSuccess) return SSSP_ERR_HIP;
   hipLaunchKernelGGL(k_tb_count_pruned, dim3(512), dim3(256), 0, st, keep, m, stats, a.status);
   if (out_row_ptr) {
