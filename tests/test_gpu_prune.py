@@ -140,3 +140,48 @@ def test_fp32_keep_mask_long_lists():
     # scale 15 has lists of several hundred entries (the workgroup ordering)
     g = gen.rmat(15, 25, weight="f32", wlo=0.5, whi=1.5)
     assert np.array_equal(gpu_keep(g), oracle.trishla(g.row_ptr, g.col, g.w))
+
+
+def test_prune_hip_graph_replays():
+    """sssp_prune captured in a HIP graph (its scan kernels then run on the
+    capturing stream alone) replays to the oracle's keep mask every time,
+    with eager prunes (concurrent scan kernels) in between."""
+    import ctypes
+
+    S = sssp_mod()
+    g = gen.rmat(13, 26)
+    ref = oracle.trishla(g.row_ptr, g.col, g.w)
+    rp, c, w = dev(g)
+    L = S.lib()
+    gc = S._csr(rp, c, w)
+    o = S.make_opts(num_partitions=16, validate=False, sync=False)
+    nb = ctypes.c_size_t(0)
+    assert L.sssp_prune(ctypes.byref(gc), ctypes.byref(o), None, None, None, None, None, None,
+                        None, ctypes.byref(nb), None) == 0
+    ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    keep = torch.empty(g.m, dtype=torch.uint8, device="cuda")
+
+    def run():
+        n2 = ctypes.c_size_t(ws.numel())
+        rc = L.sssp_prune(ctypes.byref(gc), ctypes.byref(o), S._ptr(keep), None, None, None,
+                          None, None, S._ptr(ws), ctypes.byref(n2), S._stream())
+        assert rc == 0, rc
+
+    run()  # eager, outside capture
+    torch.cuda.synchronize()
+    assert np.array_equal(keep.cpu().numpy(), ref)
+    graph = torch.cuda.CUDAGraph()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            run()
+    torch.cuda.synchronize()
+    for _ in range(3):
+        keep.fill_(7)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(keep.cpu().numpy(), ref)
+        run()
+        torch.cuda.synchronize()
+        assert np.array_equal(keep.cpu().numpy(), ref)
