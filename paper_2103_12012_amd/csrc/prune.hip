@@ -1284,36 +1284,36 @@ void launch_resident(K kernel, int bs, int grid_cus, const TbArgs &a, hipStream_
   hipLaunchKernelGGL(kernel, dim3(grid_cus * (per_cu > 0 ? per_cu : 1)), dim3(bs), 0, st, a);
 }
 
-// Side streams and fork/join events for the concurrent scan kernels: per
-// device, created on first use (default priority, non-blocking streams)
-// and kept for the life of the process.  The mutex is held while a call
-// enqueues its fork and join, so each wait pairs with that call's record.
-constexpr int SCAN_SIDE = 3;
-struct ScanSide {
-  hipStream_t s[SCAN_SIDE] = {};
-  hipEvent_t ev[1 + SCAN_SIDE] = {};
+// Side streams and fork/join events of one device: created on first use
+// (default priority, non-blocking streams) and kept for the life of the
+// process.  A call holds side_mutex() from its first fork to its last join,
+// so each wait pairs with that call's own record.
+constexpr int SIDE_STREAMS = 3, SIDE_EVENTS = 6;
+struct SideStreams {
+  hipStream_t s[SIDE_STREAMS] = {};
+  hipEvent_t ev[SIDE_EVENTS] = {};
   bool ready = false;
 };
 
-std::mutex &scan_side_mutex() {
+std::mutex &side_mutex() {
   static std::mutex mu;
   return mu;
 }
 
-// Caller holds scan_side_mutex().
-ScanSide *scan_side() {
-  static std::vector<ScanSide> per_dev;
+// Caller holds side_mutex().
+SideStreams *side_streams() {
+  static std::vector<SideStreams> per_dev;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return nullptr;
   if ((int)per_dev.size() <= dev) per_dev.resize(dev + 1);
-  ScanSide &d = per_dev[dev];
+  SideStreams &d = per_dev[dev];
   if (!d.ready) {
-    for (int i = 0; i < SCAN_SIDE; i++)
+    for (int i = 0; i < SIDE_STREAMS; i++)
       if (!d.s[i] && hipStreamCreateWithFlags(&d.s[i], hipStreamNonBlocking) != hipSuccess) {
         d.s[i] = nullptr;
         return nullptr;
       }
-    for (int i = 0; i <= SCAN_SIDE; i++)
+    for (int i = 0; i < SIDE_EVENTS; i++)
       if (!d.ev[i] && hipEventCreateWithFlags(&d.ev[i], hipEventDisableTiming) != hipSuccess) {
         d.ev[i] = nullptr;
         return nullptr;
@@ -1325,21 +1325,18 @@ ScanSide *scan_side() {
 
 // The five scan kernels (light owners, four heavy tiers).  Each drains its
 // own ticket queue with resident workgroups, so run concurrently they fill
-// each other's tails: the tiers with the longest items go to side streams
-// forked from st and joined back with events.  Under stream capture they
-// run one after another on st.
+// each other's tails: the tiers with the longest items go to the side
+// streams (forked from st with ev[2], joined back with ev[3..5]).  Without
+// side streams (stream capture) they run one after another on st.
 template <int WT>
-hipError_t launch_scan_kernels(const TbArgs &a, int grid_cus, hipStream_t st) {
+hipError_t launch_scan_kernels(const TbArgs &a, int grid_cus, hipStream_t st, SideStreams *d) {
   static_assert(NTIER == 4, "one launch per heavy tier");
   auto k_light = k_tb_light<WT>;
   auto k_t0 = k_tb_heavy<WT, 0, HM_BS, HS_SLOTS, HM_Q, HM_MARKS>;
   auto k_t1 = k_tb_heavy<WT, 1, HM_BS, HM1_SLOTS, HM_Q, HM_MARKS>;
   auto k_t2 = k_tb_heavy<WT, 2, HM_BS, HM_SLOTS, HM_Q, HM_MARKS>;
   auto k_big = k_tb_heavy<WT, T_BIG, TB_BS, HV_SLOTS, HV_Q, HV_MARKS>;
-  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-  hipError_t err = hipStreamIsCapturing(st, &cap);
-  if (err != hipSuccess) return err;
-  if (cap != hipStreamCaptureStatusNone) {
+  if (!d) {
     launch_resident(k_light, LT_BS, grid_cus, a, st);
     launch_resident(k_t0, HM_BS, grid_cus, a, st);
     launch_resident(k_t1, HM_BS, grid_cus, a, st);
@@ -1347,20 +1344,18 @@ hipError_t launch_scan_kernels(const TbArgs &a, int grid_cus, hipStream_t st) {
     launch_resident(k_big, TB_BS, grid_cus, a, st);
     return hipSuccess;
   }
-  std::lock_guard<std::mutex> lk(scan_side_mutex());
-  ScanSide *d = scan_side();
-  if (!d) return hipErrorOutOfMemory;
-  if ((err = hipEventRecord(d->ev[0], st)) != hipSuccess) return err;
-  for (int i = 0; i < SCAN_SIDE; i++)
-    if ((err = hipStreamWaitEvent(d->s[i], d->ev[0], 0)) != hipSuccess) return err;
+  hipError_t err;
+  if ((err = hipEventRecord(d->ev[2], st)) != hipSuccess) return err;
+  for (int i = 0; i < SIDE_STREAMS; i++)
+    if ((err = hipStreamWaitEvent(d->s[i], d->ev[2], 0)) != hipSuccess) return err;
   launch_resident(k_big, TB_BS, grid_cus, a, d->s[0]);
   launch_resident(k_t2, HM_BS, grid_cus, a, d->s[1]);
   launch_resident(k_t1, HM_BS, grid_cus, a, d->s[2]);
   launch_resident(k_light, LT_BS, grid_cus, a, st);
   launch_resident(k_t0, HM_BS, grid_cus, a, st);
-  for (int i = 0; i < SCAN_SIDE; i++) {
-    if ((err = hipEventRecord(d->ev[1 + i], d->s[i])) != hipSuccess) return err;
-    if ((err = hipStreamWaitEvent(st, d->ev[1 + i], 0)) != hipSuccess) return err;
+  for (int i = 0; i < SIDE_STREAMS; i++) {
+    if ((err = hipEventRecord(d->ev[3 + i], d->s[i])) != hipSuccess) return err;
+    if ((err = hipStreamWaitEvent(st, d->ev[3 + i], 0)) != hipSuccess) return err;
   }
   return hipSuccess;
 }
@@ -1439,16 +1434,39 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   }
   if (launch_excl_scan(a.ccnt, n, a.cb, tmp, st) != hipSuccess) return SSSP_ERR_HIP;
   if (m > 0) hipLaunchKernelGGL(k_csc_place, dim3(chunks), dim3(C_BS), 0, st, a);
-  hipLaunchKernelGGL(k_tb_sort_class, dim3(grid_cus), dim3(CLS_BS), 0, st, a);
-  hipLaunchKernelGGL(k_tb_sort_small, dim3(blocks), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(k_tb_sort_mid, dim3(grid_cus * 8), dim3(ORD_BS), 0, st, a);
+  // Side streams, unless st is being captured (then everything stays on st).
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess) return SSSP_ERR_HIP;
+  std::unique_lock<std::mutex> side_lock;
+  SideStreams *side = nullptr;
+  if (cap == hipStreamCaptureStatusNone) {
+    side_lock = std::unique_lock<std::mutex>(side_mutex());
+    if (!(side = side_streams())) return SSSP_ERR_HIP;
+  }
+  // The cost order (lists of at most SORT_MAX entries) runs beside the work
+  // estimate, the classification and the global tables (lists longer than
+  // HV_TCAP only): they touch disjoint data, and the scans need both.
+  hipStream_t ost = st;
+  if (side) {
+    if (hipEventRecord(side->ev[0], st) != hipSuccess ||
+        hipStreamWaitEvent(side->s[0], side->ev[0], 0) != hipSuccess)
+      return SSSP_ERR_HIP;
+    ost = side->s[0];
+  }
+  static_assert(SORT_MAX < HV_TCAP, "ordered lists never have a global table");
+  hipLaunchKernelGGL(k_tb_sort_class, dim3(grid_cus), dim3(CLS_BS), 0, ost, a);
+  hipLaunchKernelGGL(k_tb_sort_small, dim3(blocks), dim3(256), 0, ost, a);
+  hipLaunchKernelGGL(k_tb_sort_mid, dim3(grid_cus * 8), dim3(ORD_BS), 0, ost, a);
+  if (side && hipEventRecord(side->ev[1], ost) != hipSuccess) return SSSP_ERR_HIP;
   hipLaunchKernelGGL(k_tb_work, dim3(blocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_tb_classify, dim3(grid_cus * 2), dim3(CLF_BS), 0, st, a);
   hipLaunchKernelGGL(k_tb_gclear, dim3(blocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_tb_gtab, dim3(grid_cus, 16), dim3(256), 0, st, a);
+  if (side && hipStreamWaitEvent(st, side->ev[1], 0) != hipSuccess) return SSSP_ERR_HIP;
   if (ev_start && hipEventRecord((hipEvent_t)ev_start, st) != hipSuccess) return SSSP_ERR_HIP;
-  const hipError_t se = g.wtype == SSSP_W_U32 ? launch_scan_kernels<SSSP_W_U32>(a, grid_cus, st)
-                                              : launch_scan_kernels<SSSP_W_F32>(a, grid_cus, st);
+  const hipError_t se = g.wtype == SSSP_W_U32
+                            ? launch_scan_kernels<SSSP_W_U32>(a, grid_cus, st, side)
+                            : launch_scan_kernels<SSSP_W_F32>(a, grid_cus, st, side);
   if (se != hipSuccess || hipGetLastError() != hipSuccess) return SSSP_ERR_HIP;
   if (ev_stop && hipEventRecord((hipEvent_t)ev_stop, st) != hipSuccess) return SSSP_ERR_HIP;
   hipLaunchKernelGGL(k_tb_count_pruned, dim3(512), dim3(256), 0, st, keep, m, stats, a.status);
