@@ -275,6 +275,7 @@ constexpr int C_BS = 1024;
 constexpr int C_TILES = 512;   // level-1 tiles (at most)
 constexpr int CCH = 8192;      // level-2 chunk of staged arcs
 constexpr int CW = 4096;       // level-2 LDS column window
+constexpr int C_U = 4;         // arcs in flight per thread
 
 __device__ __forceinline__ int stage_x(const TbArgs &a, int p) {
   return reinterpret_cast<const int32_t *>(a.stage)[4ll * p];
@@ -312,12 +313,25 @@ __global__ __launch_bounds__(C_BS) void k_csc_scatter(TbArgs a) {
   for (int b = threadIdx.x; b < a.nb; b += C_BS)
     if (s_h[b]) s_h[b] = a.bstart[b] + atomicAdd(&a.bfill[b], s_h[b]);
   __syncthreads();
-  for (int e = e0 + threadIdx.x; e < e1; e += C_BS) {
-    const int x = a.col[e];
-    const int u = a.src[e];
-    const int wv = (int)a.w[e];
-    a.rs[e] = make_int2(x, wv);
-    a.stage[atomicAdd(&s_h[x >> a.cs], 1)] = make_int4(x, u, wv, e);
+  for (int e = e0 + threadIdx.x; e < e1; e += C_U * C_BS) {
+    int x[C_U], u[C_U], wv[C_U];
+#pragma unroll
+    for (int k = 0; k < C_U; k++) {  // C_U arcs in flight per thread
+      const int ek = e + k * C_BS;
+      if (ek < e1) {
+        x[k] = a.col[ek];
+        u[k] = a.src[ek];
+        wv[k] = (int)a.w[ek];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < C_U; k++) {
+      const int ek = e + k * C_BS;
+      if (ek < e1) {
+        a.rs[ek] = make_int2(x[k], wv[k]);
+        a.stage[atomicAdd(&s_h[x[k] >> a.cs], 1)] = make_int4(x[k], u[k], wv[k], ek);
+      }
+    }
   }
 }
 
@@ -369,19 +383,32 @@ __global__ __launch_bounds__(C_BS) void k_csc_place(TbArgs a) {
   for (int c = threadIdx.x; c < cw; c += C_BS)
     if (s_c[c]) s_c[c] = a.cb[x0 + c] + atomicAdd(&a.cfill[x0 + c], s_c[c]);
   __syncthreads();
-  for (int p = p0 + threadIdx.x; p < p1; p += C_BS) {
-    const int4 r = a.stage[p];
-    const int x = r.x, u = r.y;
-    const bool win = x - x0 < CW;
-    const int pos = win ? atomicAdd(&s_c[x - x0], 1) : a.cb[x] + atomicAdd(&a.cfill[x], 1);
-    a.cyw[pos] = make_int2(u, r.z);
-    a.ceid[pos] = r.w;
-    const int ou = a.row_ptr[u + 1] - a.row_ptr[u];
-    const int val = ou <= a.cb[x + 1] - a.cb[x] ? ou : 0;
-    if (val) {
-      if (win) atomicAdd(&s_w[x - x0], val);
-      else atomicAdd(&a.work[x], val);
-    }
+  for (int p = p0 + threadIdx.x; p < p1; p += C_U * C_BS) {
+    int4 r[C_U];
+    int ou[C_U], ix[C_U];
+#pragma unroll
+    for (int k = 0; k < C_U; k++)  // C_U entries in flight per thread
+      if (p + k * C_BS < p1) r[k] = a.stage[p + k * C_BS];
+#pragma unroll
+    for (int k = 0; k < C_U; k++)
+      if (p + k * C_BS < p1) {
+        ou[k] = a.row_ptr[r[k].y + 1] - a.row_ptr[r[k].y];
+        ix[k] = a.cb[r[k].x + 1] - a.cb[r[k].x];
+      }
+#pragma unroll
+    for (int k = 0; k < C_U; k++)
+      if (p + k * C_BS < p1) {
+        const int x = r[k].x;
+        const bool win = x - x0 < CW;
+        const int pos = win ? atomicAdd(&s_c[x - x0], 1) : a.cb[x] + atomicAdd(&a.cfill[x], 1);
+        a.cyw[pos] = make_int2(r[k].y, r[k].z);
+        a.ceid[pos] = r[k].w;
+        const int val = ou[k] <= ix[k] ? ou[k] : 0;
+        if (val) {
+          if (win) atomicAdd(&s_w[x - x0], val);
+          else atomicAdd(&a.work[x], val);
+        }
+      }
   }
   __syncthreads();
   for (int c = threadIdx.x; c < cw; c += C_BS)
