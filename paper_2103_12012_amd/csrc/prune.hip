@@ -66,10 +66,12 @@ constexpr int TK_SORT_SHORT = NTIER, TK_SORT_LONG = NTIER + 1, TK_LIGHT = NTIER 
 constexpr int HM_BS = 256;
 constexpr int HM_Q = 256;            // medium: arcs staged per batch
 constexpr int HM_MARKS = 1024;       // medium: slot marks of a round
+constexpr int HM_FSH = 3;            // 256-thread tiers: filter bits per table slot, log2
 constexpr int HV_TCAP = 8192;        // big heavy owner: longest list in an LDS table
 constexpr int HV_SLOTS = 16384;
 constexpr int HV_Q = 512;            // big: arcs staged per batch
 constexpr int HV_MARKS = 2048;       // big: slot marks of a round
+constexpr int HV_FSH = 1;            // big: filter bits per LDS table slot, log2
 constexpr int ITEM_MINQ = 32;        // an item covers at least this many arcs
 constexpr int HV_TARGET = 1 << 18;   // heavy: estimated probes per item
 constexpr int SORT_MIN = 16;         // lists of SORT_MIN+1 .. SORT_MAX entries
@@ -164,6 +166,23 @@ __device__ __forceinline__ uint32_t tb_probe(const int32_t *keys, const uint32_t
     if (k == -1) return VAL_INF;
     h = (h + 1) & mask;
   }
+}
+
+// Membership filter of a table: one bit per hash of the key (2^fbits bits,
+// fbits >= 5), set for every key of the list.  Most probes find their key
+// absent; the filter turns those into one LDS word read, so the probe loop,
+// whose longest run in a wave holds up every lane, runs only for the few
+// lanes that pass.
+__device__ __forceinline__ uint32_t tf_hash(int y, int fbits) {
+  return ((uint32_t)y * 0x85EBCA6Bu) >> (32 - fbits);
+}
+__device__ __forceinline__ void tf_set(uint32_t *filt, int fbits, int y) {
+  const uint32_t h = tf_hash(y, fbits);
+  atomicOr(&filt[h >> 5], 1u << (h & 31));
+}
+__device__ __forceinline__ bool tf_maybe(const uint32_t *filt, int fbits, int y) {
+  const uint32_t h = tf_hash(y, fbits);
+  return (filt[h >> 5] >> (h & 31)) & 1u;
 }
 
 // Smallest b >= minbits with 2^b >= 2 * len (load factor at most one half).
@@ -900,7 +919,8 @@ constexpr int STEP_STOP = 1, STEP_HIT = 2;
 template <int WT>
 __device__ __forceinline__ int tb_check(const TbArgs &a, const Owner &o, int2 yw, int other,
                                         uint32_t stop, uint32_t W, int eid, const int32_t *tkey,
-                                        const uint32_t *tval, int tmask, int tbits) {
+                                        const uint32_t *tval, int tmask, int tbits,
+                                        const uint32_t *filt, int fbits) {
   const int y = yw.x;
   const uint32_t wa = (uint32_t)yw.y;
   if (wa > stop) return STEP_STOP;
@@ -909,6 +929,7 @@ __device__ __forceinline__ int tb_check(const TbArgs &a, const Owner &o, int2 yw
   const int x = o.mode == 0 ? o.t : other;
   if (y == u || y == x) return 0;
   if (a.local && y / a.bsize != u / a.bsize) return 0;
+  if (!tf_maybe(filt, fbits, y)) return 0;
   const uint32_t wb = tb_probe(tkey, tval, tmask, tbits, y);
   if (wb != VAL_INF && Tri<WT>::lt(wa, wb, W)) {
     a.keep[eid] = 0;
@@ -976,7 +997,8 @@ __device__ __forceinline__ void scan_entries(const TbArgs &a, const Owner &o, in
                                              const int32_t *qother, const uint32_t *qstop,
                                              const uint32_t *qW,
                                              const int32_t *qeid, const int32_t *tkey,
-                                             const uint32_t *tval, int tmask, int tbits) {
+                                             const uint32_t *tval, int tmask, int tbits,
+                                             const uint32_t *filt, int fbits) {
   const int2 *list = o.mode == 0 ? a.rs : a.cyw;
   for (int base = first; base < tot; base += SCAN_U * step) {
     int q[SCAN_U], f[SCAN_U];
@@ -1000,15 +1022,17 @@ __device__ __forceinline__ void scan_entries(const TbArgs &a, const Owner &o, in
     for (int u = 0; u < SCAN_U; u++) {
       if (f[u] < 0 || f[u] >= ld_lim(&qlim[q[u]])) continue;
       lower_lim(&qlim[q[u]], tb_check<WT>(a, o, yw[u], qother[q[u]], qstop[q[u]], qW[q[u]],
-                                          qeid[q[u]], tkey, tval, tmask, tbits), f[u]);
+                                          qeid[q[u]], tkey, tval, tmask, tbits, filt, fbits),
+                f[u]);
     }
   }
 }
 
-template <int SLOTS, int QN, int NM>
+template <int SLOTS, int QN, int NM, int FSH>
 struct TbHeavy {
-  int32_t key[SLOTS];
-  uint32_t val[SLOTS];
+  int32_t key[SLOTS];     // (key and val are contiguous: the filter of a
+  uint32_t val[SLOTS];    //  global table uses them)
+  uint32_t filt[(SLOTS << FSH) / 32];  // filter of an LDS table: 2^FSH bits per slot
   int32_t qcur[QN];    // next list position to scan
   int32_t soff[QN + 1];  // live slots of the round: entry offsets,
   int32_t sq[QN];        //   arcs,
@@ -1020,9 +1044,11 @@ struct TbHeavy {
   int32_t qlim[QN];    // scan limit
 };
 constexpr int LT_MARKS = 128;
+constexpr int LT_FSH = 3;  // light: filter bits per table slot, log2
 struct TbLight {         // one per wave
   int32_t key[LT_SLOTS];
   uint32_t val[LT_SLOTS];
+  uint32_t filt[(LT_SLOTS << LT_FSH) / 32];
   int32_t qcur[WAVE];
   int32_t soff[WAVE + 1];
   int32_t sq[WAVE];
@@ -1037,10 +1063,10 @@ struct TbLight {         // one per wave
 // Heavy owners of one tier: workgroup items taken from a ticket counter;
 // the owner's table is in LDS (SLOTS slots) or, for the longest lists of
 // the big tier, in global memory.
-template <int WT, int TIER, int BS, int SLOTS, int QN, int NM>
+template <int WT, int TIER, int BS, int SLOTS, int QN, int NM, int FSH>
 __global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
   static_assert(QN <= BS && QN <= 1024 && (long long)QN * Q_DMAX < (1 << LIVE_SH), "packing");
-  __shared__ TbHeavy<SLOTS, QN, NM> H;
+  __shared__ TbHeavy<SLOTS, QN, NM, FSH> H;
   __shared__ int s_ws[BS / WAVE + 1];
   __shared__ int s_t;
   if (*a.status) return;
@@ -1061,23 +1087,41 @@ __global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
     const Owner o = make_owner(a, i);
     const int32_t *tkey;
     const uint32_t *tval;
-    int tbits;
+    uint32_t *filt;
+    int tbits, fbits;
     if (TIER == T_BIG && a.gsz[i]) {
+      // global table: the whole LDS table space holds its filter
       const long long base = (long long)a.goff[i] * G_UNIT;
       tkey = a.gkey + base;
       tval = a.gval + base;
       tbits = tb_bits(a.gsz[i] * G_UNIT / 2, 6);
-    } else {
-      tbits = tb_bits(o.llen, 6);
-      for (int s = tid; s < (1 << tbits); s += BS) {
-        H.key[s] = -1;
-        H.val[s] = VAL_INF;
-      }
+      filt = reinterpret_cast<uint32_t *>(H.key);
+      fbits = 31 - __clz(2 * SLOTS * 32);
+      for (int s = tid; s < (1 << (fbits - 5)); s += BS) filt[s] = 0u;
       __syncthreads();
       for (int p = tid; p < o.llen; p += BS) {
         uint32_t v;
         const int y = list_key(a, o, o.lbeg + p, v);
-        if (y >= 0) tb_insert(H.key, H.val, (1 << tbits) - 1, tbits, y, v);
+        if (y >= 0) tf_set(filt, fbits, y);
+      }
+      __syncthreads();
+    } else {
+      tbits = tb_bits(o.llen, 6);
+      filt = H.filt;
+      fbits = tbits + FSH;
+      for (int s = tid; s < (1 << tbits); s += BS) {
+        H.key[s] = -1;
+        H.val[s] = VAL_INF;
+      }
+      for (int s = tid; s < (1 << (fbits - 5)); s += BS) filt[s] = 0u;
+      __syncthreads();
+      for (int p = tid; p < o.llen; p += BS) {
+        uint32_t v;
+        const int y = list_key(a, o, o.lbeg + p, v);
+        if (y >= 0) {
+          tb_insert(H.key, H.val, (1 << tbits) - 1, tbits, y, v);
+          tf_set(filt, fbits, y);
+        }
       }
       __syncthreads();
       tkey = H.key;
@@ -1119,7 +1163,8 @@ __global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
         }
         __syncthreads();
         scan_entries<WT>(a, o, tid, BS, tot, H.mark, gshift, H.soff, H.sq, H.qcur, H.qlim,
-                         H.qother, H.qstop, H.qW, H.qeid, tkey, tval, tmask, tbits);
+                         H.qother, H.qstop, H.qW, H.qeid, tkey, tval, tmask, tbits, filt,
+                         fbits);
         probes += tid == 0 ? (unsigned long long)tot : 0ull;
         __syncthreads();
         if (tid < nq) H.qcur[tid] += c;
@@ -1148,15 +1193,20 @@ __global__ __launch_bounds__(LT_BS) void k_tb_light(TbArgs a) {
       const Owner o = make_owner(a, i);
       const int tbits = tb_bits(o.llen, 5);
       const int tmask = (1 << tbits) - 1;
+      const int fbits = tbits + LT_FSH;
       for (int s = lane; s < (1 << tbits); s += WAVE) {
         L.key[s] = -1;
         L.val[s] = VAL_INF;
       }
+      for (int s = lane; s < (1 << (fbits - 5)); s += WAVE) L.filt[s] = 0u;
       wave_sync();
       for (int p = lane; p < o.llen; p += WAVE) {
         uint32_t v;
         const int y = list_key(a, o, o.lbeg + p, v);
-        if (y >= 0) tb_insert(L.key, L.val, tmask, tbits, y, v);
+        if (y >= 0) {
+          tb_insert(L.key, L.val, tmask, tbits, y, v);
+          tf_set(L.filt, fbits, y);
+        }
       }
       wave_sync();
       for (int r0 = 0; r0 < o.llen; r0 += WAVE) {
@@ -1193,7 +1243,8 @@ __global__ __launch_bounds__(LT_BS) void k_tb_light(TbArgs a) {
           }
           wave_sync();
           scan_entries<WT>(a, o, lane, WAVE, tot, L.mark, gshift, L.soff, L.sq, L.qcur, L.qlim,
-                           L.qother, L.qstop, L.qW, L.qeid, L.key, L.val, tmask, tbits);
+                           L.qother, L.qstop, L.qW, L.qeid, L.key, L.val, tmask, tbits,
+                           L.filt, fbits);
           probes += lane == 0 ? (unsigned long long)tot : 0ull;
           wave_sync();
           mycur += c;
@@ -1359,10 +1410,10 @@ template <int WT>
 hipError_t launch_scan_kernels(const TbArgs &a, int grid_cus, hipStream_t st, SideStreams *d) {
   static_assert(NTIER == 4, "one launch per heavy tier");
   auto k_light = k_tb_light<WT>;
-  auto k_t0 = k_tb_heavy<WT, 0, HM_BS, HS_SLOTS, HM_Q, HM_MARKS>;
-  auto k_t1 = k_tb_heavy<WT, 1, HM_BS, HM1_SLOTS, HM_Q, HM_MARKS>;
-  auto k_t2 = k_tb_heavy<WT, 2, HM_BS, HM_SLOTS, HM_Q, HM_MARKS>;
-  auto k_big = k_tb_heavy<WT, T_BIG, TB_BS, HV_SLOTS, HV_Q, HV_MARKS>;
+  auto k_t0 = k_tb_heavy<WT, 0, HM_BS, HS_SLOTS, HM_Q, HM_MARKS, HM_FSH>;
+  auto k_t1 = k_tb_heavy<WT, 1, HM_BS, HM1_SLOTS, HM_Q, HM_MARKS, HM_FSH>;
+  auto k_t2 = k_tb_heavy<WT, 2, HM_BS, HM_SLOTS, HM_Q, HM_MARKS, HM_FSH>;
+  auto k_big = k_tb_heavy<WT, T_BIG, TB_BS, HV_SLOTS, HV_Q, HV_MARKS, HV_FSH>;
   if (!d) {
     launch_resident(k_light, LT_BS, grid_cus, a, st);
     launch_resident(k_t0, HM_BS, grid_cus, a, st);
