@@ -1531,7 +1531,7 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
       return SSSP_ERR_HIP;
     ost = side->s[0];
   }
-  static_assert(SORT_MAX < HV_TCAP, "ordered lists never have a global table");
+  static_assert(SORT_MAX <= HV_TCAP, "ordered lists never have a global table");
   hipLaunchKernelGGL(k_tb_sort_class, dim3(grid_cus), dim3(CLS_BS), 0, ost, a);
   hipLaunchKernelGGL(k_tb_sort_small, dim3(blocks), dim3(256), 0, ost, a);
   hipLaunchKernelGGL(k_tb_sort_mid, dim3(grid_cus * 8), dim3(ORD_BS), 0, ost, a);
