@@ -493,9 +493,10 @@ def main():
             "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "u32", "data": "synthetic"}
     if head is not None:
-        # the dominant single kernel is k_solve: the Trishla scan phase is four
-        # kernels (light owners and three heavy tiers), each shorter than it
-        # (see profiles/k_solve_trishla_rmat20_step.txt)
+        # the roofline names k_solve, the longest kernel that has the GPU to
+        # itself; the Trishla scan phase (reported as roofline_prune) is five
+        # kernels run concurrently on four streams, so no single one of them
+        # owns its launch time (see profiles/k_solve_trishla_rmat20_step.txt)
         dom = head["roofline_solve"]
         line.update({
             "value": round(head["gteps"], 4), "ms_per_step": round(head["ms_per_step"], 4),
