@@ -74,6 +74,7 @@ constexpr int HV_MARKS = 2048;       // big: slot marks of a round
 constexpr int HV_FSH = 1;            // big: filter bits per LDS table slot, log2
 constexpr int ITEM_MINQ = 32;        // an item covers at least this many arcs
 constexpr int HV_TARGET = 1 << 18;   // heavy: estimated probes per item
+constexpr int HV_TARGET_BIG = 1 << 20;  // big tier: larger items, fewer table rebuilds
 constexpr int SORT_MIN = 16;         // lists of SORT_MIN+1 .. SORT_MAX entries
 constexpr int SORT_MAX = 4096;       //   are sorted by cost
 constexpr int SORT_WAVE = 4 * 64;    // longest list sorted by one wave
@@ -743,7 +744,8 @@ __global__ __launch_bounds__(CLF_BS) void k_tb_classify(TbArgs a) {
     int items = 0;
     if (heavy) {
       const int cap = len / ITEM_MINQ > 1 ? len / ITEM_MINQ : 1;
-      const long long want = ((long long)wk + HV_TARGET - 1) / HV_TARGET;
+      const long long tgt = tier == T_BIG ? HV_TARGET_BIG : HV_TARGET;
+      const long long want = ((long long)wk + tgt - 1) / tgt;
       items = want < 1 ? 1 : (want > cap ? cap : (int)want);
     }
     const unsigned long long bl = __ballot(light);
