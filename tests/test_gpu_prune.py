@@ -185,3 +185,29 @@ def test_prune_hip_graph_replays():
         run()
         torch.cuda.synchronize()
         assert np.array_equal(keep.cpu().numpy(), ref)
+
+
+def test_sparse_rows_and_wide_heads_keep_masks():
+    """Shapes that reach the fallbacks of the preparation passes.
+    (1) Arcs only among two distant vertex ranges: one tail tile spans
+    ~300K empty rows, more than the tile's LDS row window, so its rows are
+    searched in row_ptr itself.  (2) Arcs among 20K vertices whose ids are
+    spread over 4M: a chunk of staged arcs spans far more columns than its
+    LDS window, so most heads take the global counters.  Both graphs hold
+    enough triangles for the keep masks to depend on the in-lists."""
+    rng = np.random.default_rng(27)
+    n = 300_000
+    ids = np.concatenate([np.arange(0, 600), np.arange(n - 600, n)])
+    u = ids[rng.integers(0, ids.size, size=16000)]
+    v = ids[rng.integers(0, ids.size, size=16000)]
+    g = gen.from_arcs(n, u, v, rng.integers(1, 40, size=u.size).astype(np.uint32))
+    ref = oracle.trishla(g.row_ptr, g.col, g.w)
+    assert (ref == 0).sum() > 100
+    assert np.array_equal(gpu_keep(g), ref)
+    ids = np.sort(rng.choice(1 << 22, size=20_000, replace=False))
+    u = ids[rng.integers(0, ids.size, size=200_000)]
+    v = ids[rng.integers(0, ids.size, size=200_000)]
+    g = gen.from_arcs(1 << 22, u, v, rng.integers(1, 40, size=u.size).astype(np.uint32))
+    ref = oracle.trishla(g.row_ptr, g.col, g.w)
+    assert (ref == 0).sum() > 100
+    assert np.array_equal(gpu_keep(g), ref)
