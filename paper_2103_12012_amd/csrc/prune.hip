@@ -941,7 +941,7 @@ __device__ __forceinline__ int tb_check(const TbArgs &a, const Owner &o, int2 yw
 }
 
 // A round lays the chunks of its live arcs end to end: live slot s holds
-// arc sq[s], entries [soff[s], soff[s+1]) (soff[nlive] = total, every
+// arc srec[s].x, entries [soff[s], soff[s+1]) (soff[nlive] = total, every
 // slot nonempty).  mark[k] is the slot holding entry k << gshift (and the
 // mark after the last one is nlive - 1), so the slot of an entry lies
 // between two marks: a binary search over a range that is almost always
@@ -991,16 +991,19 @@ constexpr int SCAN_U = 4;  // scanned entries loaded ahead per lane
 
 // Examines the flattened entries idx = first, first+step, ... < tot of the
 // staged arcs (LDS arrays of one batch): SCAN_U loads in flight per lane.
+// The chain of LDS reads ahead of each list load is kept short: the live
+// slot (marks and a short search), then its record (arc, list position of
+// the slot's first entry); the arc's record (other end, stop bound, W, id)
+// and scan limit are read while the load is in flight.  An entry past a
+// limit lowered in this round is loaded but not probed.
 template <int WT>
 __device__ __forceinline__ void scan_entries(const TbArgs &a, const Owner &o, int first,
                                              int step, int tot, const int32_t *mark, int gshift,
-                                             const int32_t *soff, const int32_t *sq,
-                                             const int32_t *qcur, int32_t *qlim,
-                                             const int32_t *qother, const uint32_t *qstop,
-                                             const uint32_t *qW,
-                                             const int32_t *qeid, const int32_t *tkey,
-                                             const uint32_t *tval, int tmask, int tbits,
-                                             const uint32_t *filt, int fbits) {
+                                             const int32_t *soff, const int2 *srec,
+                                             int32_t *qlim, const int4 *qrec,
+                                             const int32_t *tkey, const uint32_t *tval,
+                                             int tmask, int tbits, const uint32_t *filt,
+                                             int fbits) {
   const int2 *list = o.mode == 0 ? a.rs : a.cyw;
   for (int base = first; base < tot; base += SCAN_U * step) {
     int q[SCAN_U], f[SCAN_U];
@@ -1011,20 +1014,19 @@ __device__ __forceinline__ void scan_entries(const TbArgs &a, const Owner &o, in
       f[u] = -1;
       q[u] = 0;
       if (idx < tot) {
-        const int sl = locate(mark, gshift, soff, idx);
-        q[u] = sq[sl];
-        const int fu = qcur[q[u]] + (idx - soff[sl]);
-        if (fu < ld_lim(&qlim[q[u]])) {
-          f[u] = fu;
-          yw[u] = list[fu];
-        }
+        const int2 sr = srec[locate(mark, gshift, soff, idx)];
+        q[u] = sr.x;
+        f[u] = idx + sr.y;
+        yw[u] = list[f[u]];
       }
     }
 #pragma unroll
     for (int u = 0; u < SCAN_U; u++) {
       if (f[u] < 0 || f[u] >= ld_lim(&qlim[q[u]])) continue;
-      lower_lim(&qlim[q[u]], tb_check<WT>(a, o, yw[u], qother[q[u]], qstop[q[u]], qW[q[u]],
-                                          qeid[q[u]], tkey, tval, tmask, tbits, filt, fbits),
+      const int4 r = qrec[q[u]];
+      lower_lim(&qlim[q[u]],
+                tb_check<WT>(a, o, yw[u], r.x, (uint32_t)r.y, (uint32_t)r.z, r.w, tkey, tval,
+                             tmask, tbits, filt, fbits),
                 f[u]);
     }
   }
@@ -1035,15 +1037,12 @@ struct TbHeavy {
   int32_t key[SLOTS];     // (key and val are contiguous: the filter of a
   uint32_t val[SLOTS];    //  global table uses them)
   uint32_t filt[(SLOTS << FSH) / 32];  // filter of an LDS table: 2^FSH bits per slot
-  int32_t qcur[QN];    // next list position to scan
+  int4 qrec[QN];        // per arc: other end, stop bound, W, arc id
+  int32_t qcur[QN];      // per arc: next list position to scan
+  int32_t qlim[QN];      // per arc: scan limit
   int32_t soff[QN + 1];  // live slots of the round: entry offsets,
-  int32_t sq[QN];        //   arcs,
+  int2 srec[QN];         //   (arc, list position of entry 0 of the round),
   int32_t mark[NM + 1];  //   and marks
-  uint32_t qW[QN];
-  int32_t qeid[QN];
-  int32_t qother[QN];  // other end
-  uint32_t qstop[QN];  // stop bound
-  int32_t qlim[QN];    // scan limit
 };
 constexpr int LT_MARKS = 128;
 constexpr int LT_FSH = 3;  // light: filter bits per table slot, log2
@@ -1051,15 +1050,11 @@ struct TbLight {         // one per wave
   int32_t key[LT_SLOTS];
   uint32_t val[LT_SLOTS];
   uint32_t filt[(LT_SLOTS << LT_FSH) / 32];
-  int32_t qcur[WAVE];
-  int32_t soff[WAVE + 1];
-  int32_t sq[WAVE];
-  int32_t mark[LT_MARKS + 1];
-  uint32_t qW[WAVE];
-  int32_t qeid[WAVE];
-  int32_t qother[WAVE];
-  uint32_t qstop[WAVE];
+  int4 qrec[WAVE];
   int32_t qlim[WAVE];
+  int32_t soff[WAVE + 1];
+  int2 srec[WAVE];
+  int32_t mark[LT_MARKS + 1];
 };
 
 // Heavy owners of one tier: workgroup items taken from a ticket counter;
@@ -1139,10 +1134,7 @@ __global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
         const Query q = make_query(a, o, o.lbeg + r0 + tid);
         H.qcur[tid] = q.beg;
         H.qlim[tid] = q.beg + q.len;
-        H.qW[tid] = q.W;
-        H.qeid[tid] = q.eid;
-        H.qother[tid] = q.other;
-        H.qstop[tid] = q.stop;
+        H.qrec[tid] = make_int4(q.other, (int)q.stop, (int)q.W, q.eid);
       }
       __syncthreads();
       for (int D = Q_D0;; D = min(2 * D, Q_DMAX)) {
@@ -1155,7 +1147,7 @@ __global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
         const int gshift = mark_shift(tot, NM, D);
         if (c > 0) {
           const int sl = run >> LIVE_SH, off = run & ((1 << LIVE_SH) - 1);
-          H.sq[sl] = tid;
+          H.srec[sl] = make_int2(tid, H.qcur[tid] - off);
           H.soff[sl] = off;
           put_marks(H.mark, gshift, sl, off, c);
         }
@@ -1164,9 +1156,8 @@ __global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
           H.mark[((tot - 1) >> gshift) + 1] = (packed >> LIVE_SH) - 1;
         }
         __syncthreads();
-        scan_entries<WT>(a, o, tid, BS, tot, H.mark, gshift, H.soff, H.sq, H.qcur, H.qlim,
-                         H.qother, H.qstop, H.qW, H.qeid, tkey, tval, tmask, tbits, filt,
-                         fbits);
+        scan_entries<WT>(a, o, tid, BS, tot, H.mark, gshift, H.soff, H.srec, H.qlim, H.qrec, tkey,
+                         tval, tmask, tbits, filt, fbits);
         probes += tid == 0 ? (unsigned long long)tot : 0ull;
         __syncthreads();
         if (tid < nq) H.qcur[tid] += c;
@@ -1218,10 +1209,7 @@ __global__ __launch_bounds__(LT_BS) void k_tb_light(TbArgs a) {
           const Query q = make_query(a, o, o.lbeg + r0 + lane);
           mycur = q.beg;
           L.qlim[lane] = q.beg + q.len;
-          L.qW[lane] = q.W;
-          L.qeid[lane] = q.eid;
-          L.qother[lane] = q.other;
-          L.qstop[lane] = q.stop;
+          L.qrec[lane] = make_int4(q.other, (int)q.stop, (int)q.W, q.eid);
         }
         wave_sync();
         for (int D = Q_D0;; D = min(2 * D, Q_DMAX)) {
@@ -1231,11 +1219,10 @@ __global__ __launch_bounds__(LT_BS) void k_tb_light(TbArgs a) {
           const int tot = packed & ((1 << LIVE_SH) - 1);
           if (tot == 0) break;
           const int gshift = mark_shift(tot, LT_MARKS, D);
-          if (lane < nq) L.qcur[lane] = mycur;
           if (c > 0) {
             const int run = incl - live_pack(c);
             const int sl = run >> LIVE_SH, off = run & ((1 << LIVE_SH) - 1);
-            L.sq[sl] = lane;
+            L.srec[sl] = make_int2(lane, mycur - off);
             L.soff[sl] = off;
             put_marks(L.mark, gshift, sl, off, c);
           }
@@ -1244,9 +1231,8 @@ __global__ __launch_bounds__(LT_BS) void k_tb_light(TbArgs a) {
             L.mark[((tot - 1) >> gshift) + 1] = (packed >> LIVE_SH) - 1;
           }
           wave_sync();
-          scan_entries<WT>(a, o, lane, WAVE, tot, L.mark, gshift, L.soff, L.sq, L.qcur, L.qlim,
-                           L.qother, L.qstop, L.qW, L.qeid, L.key, L.val, tmask, tbits,
-                           L.filt, fbits);
+          scan_entries<WT>(a, o, lane, WAVE, tot, L.mark, gshift, L.soff, L.srec, L.qlim, L.qrec,
+                           L.key, L.val, tmask, tbits, L.filt, fbits);
           probes += lane == 0 ? (unsigned long long)tot : 0ull;
           wave_sync();
           mycur += c;
