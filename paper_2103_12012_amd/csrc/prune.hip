@@ -1258,23 +1258,31 @@ __global__ void k_tb_count_pruned(const uint8_t *keep, int m, sssp_stats *stats,
 }
 
 // ------------------------------------------------------------ compaction
-// pos = exclusive scan of keep over all arcs: kept arc e goes to pos[e], and
-// the pruned row u starts at pos[row_ptr[u]] (order is preserved).
+// The kept arcs before arc e number pos[e] + toff[e / SCAN_TILE] (a tile-local
+// scan of keep plus the tile's offset; pos[m] is the kept total): kept arc
+// e goes there, and the pruned row u starts at that count for row_ptr[u]
+// (order is preserved).
+__device__ __forceinline__ int kept_before(const int32_t *pos, const int32_t *toff, int m,
+                                           int e) {
+  if (e <= 0) return 0;
+  return e >= m ? pos[m] : pos[e] + toff[e / SCAN_TILE];
+}
+
 __global__ void k_compact(const int32_t *row_ptr, const int32_t *col, const uint32_t *w,
                           const uint8_t *keep, int n, int m, const int32_t *pos,
-                          int32_t *out_row_ptr, int32_t *out_col, uint32_t *out_w,
-                          int32_t *edge_map, const int32_t *status) {
+                          const int32_t *toff, int32_t *out_row_ptr, int32_t *out_col,
+                          uint32_t *out_w, int32_t *edge_map, const int32_t *status) {
   if (*status) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int stride = gridDim.x * blockDim.x;
   for (int e = t; e < m; e += stride)
     if (keep[e]) {
-      const int p = pos[e];
+      const int p = kept_before(pos, toff, m, e);
       out_col[p] = col[e];
       out_w[p] = w[e];
       edge_map[p] = e;
     }
-  for (int u = t; u <= n; u += stride) out_row_ptr[u] = pos[row_ptr[u]];
+  for (int u = t; u <= n; u += stride) out_row_ptr[u] = kept_before(pos, toff, m, row_ptr[u]);
 }
 
 // ------------------------------------------------------------ host side
@@ -1537,9 +1545,10 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   if (ev_stop && hipEventRecord((hipEvent_t)ev_stop, st) != hipSuccess) return SSSP_ERR_HIP;
   hipLaunchKernelGGL(k_tb_count_pruned, dim3(512), dim3(256), 0, st, keep, m, stats, a.status);
   if (out_row_ptr) {
-    if (launch_excl_scan_u8(keep, m, pos, tmp, st) != hipSuccess) return SSSP_ERR_HIP;
+    if (launch_tile_scan_u8(keep, m, pos, tmp, st) != hipSuccess) return SSSP_ERR_HIP;
     hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(256), 0, st, g.row_ptr, g.col,
-                       static_cast<const uint32_t *>(g.w), keep, n, m, pos, out_row_ptr, out_col,
+                       static_cast<const uint32_t *>(g.w), keep, n, m, pos, tmp, out_row_ptr,
+                       out_col,
                        static_cast<uint32_t *>(out_w), edge_map, a.status);
   }
   hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(64), 0, st, a.status, stats);

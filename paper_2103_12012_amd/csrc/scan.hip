@@ -8,7 +8,7 @@ namespace sssp_impl {
 
 constexpr int SCAN_BS = 256;
 constexpr int SCAN_EPT = 8;
-constexpr int SCAN_TILE = SCAN_BS * SCAN_EPT;
+static_assert(SCAN_TILE == SCAN_BS * SCAN_EPT, "tile of the scans");
 
 template <typename T>
 __global__ __launch_bounds__(SCAN_BS) void k_scan_tiles(const T *in, int n, int32_t *out,
@@ -89,9 +89,14 @@ hipError_t launch_excl_scan(const int32_t *in, int n, int32_t *out, int32_t *tmp
   return excl_scan_t(in, n, out, tmp, st);
 }
 
-hipError_t launch_excl_scan_u8(const uint8_t *in, int n, int32_t *out, int32_t *tmp,
+hipError_t launch_tile_scan_u8(const uint8_t *in, int n, int32_t *out, int32_t *tile_off,
                                hipStream_t st) {
-  return excl_scan_t(in, n, out, tmp, st);
+  const int ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+  if (ntiles > 0)
+    hipLaunchKernelGGL(k_scan_tiles<uint8_t>, dim3(ntiles), dim3(SCAN_BS), 0, st, in, n, out,
+                       tile_off);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_BS), 0, st, tile_off, ntiles, out + n);
+  return hipGetLastError();
 }
 
 }  // namespace sssp_impl
