@@ -1038,7 +1038,6 @@ struct TbHeavy {
   uint32_t val[SLOTS];    //  global table uses them)
   uint32_t filt[(SLOTS << FSH) / 32];  // filter of an LDS table: 2^FSH bits per slot
   int4 qrec[QN];        // per arc: other end, stop bound, W, arc id
-  int32_t qcur[QN];      // per arc: next list position to scan
   int32_t qlim[QN];      // per arc: scan limit
   int32_t soff[QN + 1];  // live slots of the round: entry offsets,
   int2 srec[QN];         //   (arc, list position of entry 0 of the round),
@@ -1130,16 +1129,17 @@ __global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
     const int p1 = (int)((long long)o.llen * (k + 1) / ni);
     for (int r0 = p0; r0 < p1; r0 += QN) {
       const int nq = min(QN, p1 - r0);
+      int cur = 0;  // next list position of this thread's arc
       if (tid < nq) {
         const Query q = make_query(a, o, o.lbeg + r0 + tid);
-        H.qcur[tid] = q.beg;
+        cur = q.beg;
         H.qlim[tid] = q.beg + q.len;
         H.qrec[tid] = make_int4(q.other, (int)q.stop, (int)q.W, q.eid);
       }
       __syncthreads();
       for (int D = Q_D0;; D = min(2 * D, Q_DMAX)) {
         int c = 0;
-        if (tid < nq) c = max(0, min(D, H.qlim[tid] - H.qcur[tid]));
+        if (tid < nq) c = max(0, min(D, H.qlim[tid] - cur));
         int packed;
         const int run = block_excl_scan<BS>(live_pack(c), s_ws, &packed);
         const int tot = packed & ((1 << LIVE_SH) - 1);
@@ -1147,7 +1147,7 @@ __global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
         const int gshift = mark_shift(tot, NM, D);
         if (c > 0) {
           const int sl = run >> LIVE_SH, off = run & ((1 << LIVE_SH) - 1);
-          H.srec[sl] = make_int2(tid, H.qcur[tid] - off);
+          H.srec[sl] = make_int2(tid, cur - off);
           H.soff[sl] = off;
           put_marks(H.mark, gshift, sl, off, c);
         }
@@ -1160,8 +1160,7 @@ __global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
                          tval, tmask, tbits, filt, fbits);
         probes += tid == 0 ? (unsigned long long)tot : 0ull;
         __syncthreads();
-        if (tid < nq) H.qcur[tid] += c;
-        __syncthreads();
+        cur += c;
       }
     }
     __syncthreads();
