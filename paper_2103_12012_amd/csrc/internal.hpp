@@ -149,6 +149,27 @@ __device__ __forceinline__ int block_excl_scan(int x, int *ws, int *total) {
   return r;
 }
 
+// Exclusive scan of one int per thread over the block with a single
+// barrier: every thread adds up the totals of the waves before its own.
+// ws (BS/64 ints) must not be written again before another barrier.
+template <int BS>
+__device__ __forceinline__ int block_excl_scan1(int x, int *ws, int *total) {
+  constexpr int NW = BS / WAVE;
+  const int wid = threadIdx.x / WAVE;
+  const int incl = wave_incl_scan(x);
+  if (lane_id() == WAVE - 1) ws[wid] = incl;
+  __syncthreads();
+  int before = 0, all = 0;
+#pragma unroll
+  for (int k = 0; k < NW; k++) {
+    const int t = ws[k];
+    before += k < wid ? t : 0;
+    all += t;
+  }
+  *total = all;
+  return before + incl - x;
+}
+
 // ------------------------------------------------------------ solve descriptors
 // One independent single-source problem of a (possibly batched) solve.
 struct SolveDesc {

@@ -435,7 +435,8 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
       }
       int tot;
       const int before = s_nlist;
-      int j = before + block_excl_scan<BS>(__popc(bits), s_ws, &tot);
+      // one barrier: s_ws is next written after this iteration's last barrier
+      int j = before + block_excl_scan1<BS>(__popc(bits), s_ws, &tot);
       uint32_t back = 0;
       for (uint32_t b = bits; b; b &= b - 1) {
         if (j < FCAP) s_rs[j] = wi * 32 + __ffs(b) - 1;
@@ -579,7 +580,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
         lsum += degs[j];
       }
       int tot;
-      int run = block_excl_scan<BS>(lsum, s_ws, &tot);
+      int run = block_excl_scan1<BS>(lsum, s_ws, &tot);  // s_ws reused after later barriers
 #pragma unroll
       for (int j = 0; j < EPT; j++) {
         const int k = tid * EPT + j;
