@@ -31,6 +31,34 @@ namespace sssp_impl {
 
 constexpr int FCAP = 1024;  // frontier vertices staged in LDS per round
 constexpr int MAXB = 32768; // largest partition (vertices)
+constexpr int ACT_SLOTS = 512;  // deferred unit activations per batch (LDS hash)
+constexpr int ACT_FEW = 32;     // at most this many units recorded: wake them every round
+
+// Activating the unit a push lands in (its pending minimum and active bit)
+// is deferred: the pushes of a batch are gathered per destination unit in
+// an LDS table, and each unit is published once.  With at most ACT_FEW
+// units recorded (a thin frontier crossing into a neighbour, where waking
+// it soon is the critical path) the table is published at the end of every
+// round, otherwise at the end of the batch, before the batch's pending-work
+// surplus is returned.  One atomic min and one atomic or per unit replace
+// one of each per cross-partition push, which all workgroups aimed at the
+// same few hundred words.
+//
+// Records a push into unit gu at distance d; false when the table is
+// crowded (the caller activates directly).
+__device__ __forceinline__ bool act_defer(int32_t *keys, uint32_t *dmin, int *nrec, int gu, uint32_t d) {
+  uint32_t h = ((uint32_t)gu * 2654435761u) >> 23;  // 512 slots
+  for (int probe = 0; probe < 8; probe++) {
+    const int old = atomicCAS(&keys[h], -1, gu);
+    if (old == -1) atomicAdd(nrec, 1);
+    if (old == -1 || old == gu) {
+      atomicMin(&dmin[h], d);
+      return true;
+    }
+    h = (h + 1) & (ACT_SLOTS - 1);
+  }
+  return false;
+}
 constexpr int MAX_ROUNDS_PER_BATCH = 256;
 // Pending-count raise of one batch: above MAX_ROUNDS_PER_BATCH * (2^31 - 1)
 // inbox bits, and 2^50 per workgroup keeps the sum far from overflow.
@@ -230,9 +258,17 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
   __shared__ uint32_t s_mark[MAXB / 32];   // partition-local dedupe of s_nv
   __shared__ int s_ncnt;
   __shared__ long long s_tot, s_exp;
+  __shared__ int32_t s_actk[ACT_SLOTS];   // deferred activations: unit (-1 = free)
+  __shared__ uint32_t s_actd[ACT_SLOTS];  //   and the least distance pushed into it
+  __shared__ int s_actn;                  //   units recorded
 
   const int tid0 = threadIdx.x;
   for (int i = tid0; i < MAXB / 32; i += BS) s_mark[i] = 0u;
+  for (int i = tid0; i < ACT_SLOTS; i += BS) {
+    s_actk[i] = -1;
+    s_actd[i] = 0xFFFFFFFFu;
+  }
+  if (tid0 == 0) s_actn = 0;
   Ctrl *ctrl = a.ctrl;
   if (tid0 == 0) {
     s_exit = ld_rlx(&ctrl->status) != 0;
@@ -694,8 +730,10 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
           const int q = v[j] / bsize;
           if (q != part) {
             const int gu = unit0 + q;
-            amin(&unit_min[gu], (unsigned long long)nd[j]);
-            aor(&abits[abw(gu)], 1u << (gu & 31));
+            if (!act_defer(s_actk, s_actd, &s_actn, gu, nd[j])) {
+              amin(&unit_min[gu], (unsigned long long)nd[j]);
+              aor(&abits[abw(gu)], 1u << (gu & 31));
+            }
           } else {
             pmin = nd[j] < pmin ? nd[j] : pmin;
           }
@@ -716,6 +754,19 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
         s_exp += cur_cnt;
       }
       __syncthreads();
+      if (s_actn <= ACT_FEW) {  // few units pushed into: wake them now
+        for (int i = tid; i < ACT_SLOTS; i += BS) {
+          const int gu = s_actk[i];
+          if (gu >= 0) {
+            amin(&unit_min[gu], (unsigned long long)s_actd[i]);
+            aor(&abits[abw(gu)], 1u << (gu & 31));
+            s_actk[i] = -1;
+            s_actd[i] = 0xFFFFFFFFu;
+          }
+        }
+        __syncthreads();
+        if (tid == 0) s_actn = 0;
+      }
       const int ncnt = uni(min(s_ncnt, FCAP));
       nround++;
       if (ncnt == 0) break;
@@ -746,6 +797,19 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
       __syncthreads();
     }
 
+    // deferred activations of the units this batch pushed into: published
+    // before the settle below returns the batch's surplus of pending work
+    for (int i = tid; i < ACT_SLOTS; i += BS) {
+      const int gu = s_actk[i];
+      if (gu >= 0) {
+        amin(&unit_min[gu], (unsigned long long)s_actd[i]);
+        aor(&abits[abw(gu)], 1u << (gu & 31));
+        s_actk[i] = -1;
+        s_actd[i] = 0xFFFFFFFFu;
+      }
+    }
+    if (tid == 0) s_actn = 0;
+    __syncthreads();
     // ------------------------------------------------------ 5. settle
     if (tid == 0) {
       // every consequence of this batch is published: return the surplus
