@@ -186,7 +186,7 @@ SolveLayout solve_layout(int nsolves, const std::vector<int> &ns, int nunits) {
     off += align_up(bytes ? bytes : 1, 256);
     return at;
   };
-  const int nabw = (nunits + 31) / 32;
+  const int nabw = (nunits + ABW_UNITS - 1) / ABW_UNITS;
   L.ctrl = take(sizeof(Ctrl));
   L.desc = take(sizeof(SolveDesc) * (size_t)nsolves);
   L.unit_solve = take(sizeof(int32_t) * (size_t)nunits);
@@ -236,7 +236,7 @@ int run_solves(std::vector<SolveDesc> &descs, const SolveLayout &L, int nunits, 
   a.ctrl = reinterpret_cast<Ctrl *>(ws + L.ctrl);
   a.stats = stats;
   a.nunits = nunits;
-  a.nabw = (nunits + 31) / 32;
+  a.nabw = (nunits + ABW_UNITS - 1) / ABW_UNITS;
   a.max_rounds = o.max_rounds;
   a.num_solves = (int)descs.size();
   a.window = DELTA_INF;

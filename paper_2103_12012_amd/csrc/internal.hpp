@@ -15,6 +15,7 @@ constexpr unsigned long long LABEL_INF = ~0ull;
 constexpr unsigned long long DELTA_INF = ~0ull;
 constexpr unsigned long long DELTA_AUTO = 0ull;  // bucket width set on the device
 constexpr int ABW_STRIDE = 32;                   // active-unit bitmap word stride
+constexpr int ABW_UNITS = 8;                     // units per active-unit bitmap word
 
 // ------------------------------------------------------------ atomics
 // Every datum that several workgroups write or read while a kernel runs is
@@ -209,7 +210,7 @@ struct SolveArgs {
   const SolveDesc *desc;       // num_solves descriptors
   int32_t *unit_solve;         // unit -> solve index
   unsigned long long *unit_min;  // per unit: least pending distance (lower bound)
-  uint32_t *abits;             // active-unit bitmap, one 32-unit word per
+  uint32_t *abits;             // active-unit bitmap, one 8-unit word per
                                // 128-byte line (ABW_STRIDE words apart)
   Ctrl *ctrl;
   sssp_stats *stats;

@@ -118,11 +118,13 @@ template <> struct Dist<SSSP_W_F32> {
 };
 
 // ------------------------------------------------------------------ setup
-// Word of the active-unit bitmap holding unit u: each 32-unit word sits on a
-// 128-byte line of its own (ABW_STRIDE words apart), since every push that
-// activates a unit and every claim is an atomic on that word, and one shared
-// line serialises them all.
-__device__ __forceinline__ int abw(int u) { return (u >> 5) * ABW_STRIDE; }
+// Word of the active-unit bitmap holding unit u, and u's bit in it: each word
+// holds 8 units and sits on a 128-byte line of its own (ABW_STRIDE words
+// apart), since every wakeup and every claim of a unit is an atomic on that
+// word; fewer units per line means less contention (32 per word: 10% slower
+// on R-MAT 20), and the pick still reads one word per 8 units.
+__device__ __forceinline__ int abw(int u) { return (u / ABW_UNITS) * ABW_STRIDE; }
+__device__ __forceinline__ uint32_t abit(int u) { return 1u << (u % ABW_UNITS); }
 
 
 // Writes descriptors carried in the kernel arguments into the workspace, so
@@ -169,7 +171,7 @@ __global__ void k_init(SolveArgs a) {
   }
   if (t == 0) {
     const int u = d.unit0 + ps;
-    aor(&a.abits[abw(u)], 1u << (u & 31));
+    aor(&a.abits[abw(u)], abit(u));
   }
 }
 
@@ -325,7 +327,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
         for (int j = 0; j < 4; j++) {
           const int u = u0 + j * BS + tid;
           umv[j] = ~0ull;
-          const bool act = u < a.nunits && ((wv[j] >> (u & 31)) & 1u);
+          const bool act = u < a.nunits && (wv[j] & abit(u)) != 0u;
           if (act) umv[j] = ld_rlx(&unit_min[u]);
           if (u0 == 0) {
             um0[j] = umv[j];
@@ -354,7 +356,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
             act = (act0 >> j) & 1u;
             d = um0[j];
           } else {
-            act = u < a.nunits && ((ld_rlx(&abits[abw(u)]) >> (u & 31)) & 1u);
+            act = u < a.nunits && (ld_rlx(&abits[abw(u)]) & abit(u)) != 0u;
             d = act ? ld_rlx(&unit_min[u]) : ~0ull;
           }
           if (act && (d == ~0ull || gmin == ~0ull || window == DELTA_INF ||
@@ -384,7 +386,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
           if (bi < 0) break;
           tried |= 1u << bi;
           const int u = (int)unit_unmix((uint32_t)bk, mixkey);
-          const uint32_t mb = 1u << (u & 31);
+          const uint32_t mb = abit(u);
           if (aand_acq(&abits[abw(u)], ~mb) & mb) {
             s_unit = u;
             s_gmin = gmin;
@@ -732,7 +734,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
             const int gu = unit0 + q;
             if (!act_defer(s_actk, s_actd, &s_actn, gu, nd[j])) {
               amin(&unit_min[gu], (unsigned long long)nd[j]);
-              aor(&abits[abw(gu)], 1u << (gu & 31));
+              aor(&abits[abw(gu)], abit(gu));
             }
           } else {
             pmin = nd[j] < pmin ? nd[j] : pmin;
@@ -759,7 +761,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
           const int gu = s_actk[i];
           if (gu >= 0) {
             amin(&unit_min[gu], (unsigned long long)s_actd[i]);
-            aor(&abits[abw(gu)], 1u << (gu & 31));
+            aor(&abits[abw(gu)], abit(gu));
             s_actk[i] = -1;
             s_actd[i] = 0xFFFFFFFFu;
           }
@@ -803,7 +805,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
       const int gu = s_actk[i];
       if (gu >= 0) {
         amin(&unit_min[gu], (unsigned long long)s_actd[i]);
-        aor(&abits[abw(gu)], 1u << (gu & 31));
+        aor(&abits[abw(gu)], abit(gu));
         s_actk[i] = -1;
         s_actd[i] = 0xFFFFFFFFu;
       }
@@ -825,7 +827,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
         if (!trunc && (window == DELTA_INF || Dist<WT>::within(rem, s_gmin, window)))
           s_stay = unit;
         else
-          aor(&abits[abw(unit)], 1u << (unit & 31));
+          aor(&abits[abw(unit)], abit(unit));
       }
       st_tot += (unsigned long long)s_tot;
       st_upd += s_upd;
