@@ -13,8 +13,10 @@
 //  * It expands the frontier edge-parallel: coalesced CSR streaming, one
 //    64-bit atomic min per arc on the head's packed (dist << 32 | edge id)
 //    label.  A strictly lower distance sets the head's inbox bit; a head in
-//    another unit also raises that unit's active bit -- the asynchronous
-//    Bellman-Ford exchange between partitions (send_msg / recv_msgs).
+//    another unit also wakes that unit (its pending minimum and active bit,
+//    gathered per unit in LDS and published once per round or batch) --
+//    the asynchronous Bellman-Ford exchange between partitions (send_msg /
+//    recv_msgs).
 //  * Ctrl::work counts inbox bits plus vertices in flight.  It is raised
 //    before work is published and lowered after its consequences are
 //    published, so it reaches zero exactly when the global fixed point is
