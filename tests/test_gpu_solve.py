@@ -242,3 +242,22 @@ def test_largest_partition_block():
     assert solver.stats.read()["num_partitions"] == 3
     assert_solve_parity(g, 0, (dist.cpu().numpy().view(np.uint32), pred.cpu().numpy(),
                                pe.cpu().numpy()))
+
+
+def test_hub_wakes_more_units_than_the_wakeup_table():
+    """A hub with arcs into 20000 single-vertex partitions: one batch pushes
+    into far more units than the LDS table that gathers the wakeups holds
+    (512 slots), so most wakeups take the direct path; a second layer of
+    arcs among the leaves keeps several rounds of cross-partition pushes
+    going.  Exact against the oracle, and with several workgroup shapes."""
+    n = 20001
+    rng = np.random.default_rng(6)
+    u = np.concatenate([np.zeros(n - 1, np.int64), rng.integers(1, n, size=40000)])
+    v = np.concatenate([np.arange(1, n), rng.integers(1, n, size=40000)])
+    w = rng.integers(1, 30, size=u.size).astype(np.uint32)
+    keep = u != v
+    g = gen.from_arcs(n, u[keep], v[keep], w[keep])
+    ref = oracle.solve(g.row_ptr, g.col, g.w, 0)
+    for kw in (dict(num_partitions=n), dict(num_partitions=n, wg_size=256, lag=-1),
+               dict(num_partitions=4000, delta=-1.0)):
+        assert_solve_parity(g, 0, gpu_solve(g, 0, **kw), ref)
