@@ -94,8 +94,8 @@ typedef struct {
                               average degree is >= 8, 16x below)          */
   int32_t num_partitions;  /* P, 1D blocks of ceil(n/P) vertices; 0 = auto
                               (cache, else blocks of 4096 vertices when the
-                              average degree is >= 8 and 32768 below);
-                              raised so that a block has at most 32768 vertices */
+                              average degree is >= 8 and 65536 below);
+                              raised so that a block has at most 65536 vertices */
   int32_t wg_size;         /* threads per workgroup: 256, 512 or 1024; 0 = auto
                               (cache, else 512 when the average degree is
                               >= 8 and 256 below)                          */

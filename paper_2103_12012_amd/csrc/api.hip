@@ -114,13 +114,13 @@ unsigned long long delta_units(double delta, int wtype) {
 // low-diameter graphs (average degree >= 8) take narrow buckets (half the
 // mean arc cost) and 4096-vertex blocks; sparse ones, typically of high
 // diameter with thin frontiers, take wide buckets (16 mean costs) so that a
-// bucket spans many hops, and 32768-vertex blocks.
+// bucket spans many hops, and 65536-vertex blocks.
 static bool dense_graph(int n, long long m) { return n > 0 && m >= 8ll * n; }
 
 float auto_delta_factor(int n, long long m) { return dense_graph(n, m) ? 0.5f : 16.0f; }
 
 int default_parts(int n, long long m) {
-  const long long b = dense_graph(n, m) ? 4096 : 32768;
+  const long long b = dense_graph(n, m) ? 4096 : 65536;
   long long p = ((long long)n + b - 1) / b;
   if (p < 1) p = 1;
   if (p > 65536) p = 65536;
@@ -139,7 +139,7 @@ SolvePlan make_plan(const sssp_csr &g, const sssp_opts &o) {
                                : (have && tuned.num_partitions > 0 ? tuned.num_partitions
                                                                    : default_parts(g.n, g.m));
   if (P > g.n) P = g.n;
-  const int pmin = (int)(((long long)g.n + 32767) / 32768);  // blocks <= 32768 vertices
+  const int pmin = (int)(((long long)g.n + 65535) / 65536);  // blocks <= 65536 vertices
   if (P < pmin) P = pmin;
   pl.bsize = (g.n + P - 1) / P;
   pl.nparts = (g.n + pl.bsize - 1) / pl.bsize;  // non-empty blocks only

@@ -32,7 +32,7 @@
 namespace sssp_impl {
 
 constexpr int FCAP = 1024;  // frontier vertices staged in LDS per round
-constexpr int MAXB = 32768; // largest partition (vertices)
+constexpr int MAXB = 65536; // largest partition (vertices): LDS dedupe bitmap and gather mask
 constexpr int ACT_SLOTS = 512;  // deferred unit activations per batch (LDS hash)
 constexpr int ACT_FEW = 32;     // at most this many units recorded: wake them every round
 
@@ -251,7 +251,8 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
   __shared__ uint32_t s_vd[FCAP];     // their distances (round 0)
   __shared__ uint32_t s_d[FCAP];      // gather: listed distances; relax: frontier distances
   __shared__ int32_t s_rs[FCAP];      // gather: listed vertices;  relax: first arc of each
-  __shared__ int32_t s_off[FCAP + 1]; // gather: near mask per word; relax: degree prefix
+  __shared__ int32_t s_off[FCAP + 1]; // relax: degree prefix
+  __shared__ uint32_t s_fm[MAXB / 32]; // gather: far mask per inbox word
   __shared__ int s_ws[NW + 1];
   __shared__ unsigned long long s_red[NW];
   __shared__ SolveDesc s_desc;
@@ -520,7 +521,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
         }
       }
     }
-    for (int i = tid; i <= whi - wlo; i += BS) s_off[i] = 0;
+    for (int i = tid; i <= whi - wlo; i += BS) s_fm[i] = 0u;
     lmin = wave_min(lmin);
     if (lane == 0) s_red[wid] = lmin;
     __syncthreads();
@@ -540,7 +541,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
         s_vd[slot] = dv;
       } else {
         far = dv < far ? dv : far;
-        atomicOr((unsigned int *)&s_off[(v >> 5) - wlo], 1u << (v & 31));
+        atomicOr(&s_fm[(v >> 5) - wlo], 1u << (v & 31));
       }
     }
     far = wave_min(far);
@@ -548,7 +549,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
     __syncthreads();
     unsigned int putback = 0;
     for (int i = tid; i <= whi - wlo; i += BS) {
-      const uint32_t fb = (uint32_t)s_off[i];
+      const uint32_t fb = s_fm[i];
       if (fb) putback += __popc(fb & ~aor(&dirty[wlo + i], fb));
     }
     putback = wave_sum(putback);

@@ -232,16 +232,19 @@ def test_hub_floods_frontier_capacity():
 
 
 def test_largest_partition_block():
-    """P = 1 on a graph of 70000 vertices is raised so that no block exceeds
-    32768 vertices (the LDS dedupe bitmap); the result is exact."""
-    g = gen.uniform(70000, 300000, seed=8)
+    """P = 1 on a graph of 140000 vertices is raised so that no block exceeds
+    65536 vertices (the LDS dedupe bitmap and gather mask of a partition);
+    blocks of exactly 65536 vertices (P = 2 on 131072) fill both; the
+    results are exact."""
     S = sssp_mod()
-    rp, c, w = dev(g)
-    solver = S.Solver(rp, c, w, num_partitions=1, stats=True)
-    dist, pred, pe = solver(0, sync=True)
-    assert solver.stats.read()["num_partitions"] == 3
-    assert_solve_parity(g, 0, (dist.cpu().numpy().view(np.uint32), pred.cpu().numpy(),
-                               pe.cpu().numpy()))
+    for n, P, want in ((140000, 1, 3), (131072, 2, 2)):
+        g = gen.uniform(n, 4 * n, seed=8)
+        rp, c, w = dev(g)
+        solver = S.Solver(rp, c, w, num_partitions=P, stats=True)
+        dist, pred, pe = solver(0, sync=True)
+        assert solver.stats.read()["num_partitions"] == want
+        assert_solve_parity(g, 0, (dist.cpu().numpy().view(np.uint32), pred.cpu().numpy(),
+                                   pe.cpu().numpy()))
 
 
 def test_hub_wakes_more_units_than_the_wakeup_table():
