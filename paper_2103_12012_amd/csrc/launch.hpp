@@ -20,13 +20,11 @@ __global__ void k_copy_status(const int32_t *status, sssp_stats *stats);
 size_t scan_tmp_bytes(int n);
 hipError_t launch_excl_scan(const int32_t *in, int n, int32_t *out, int32_t *tmp,
                             hipStream_t st);
-// Tile-local exclusive scan of uint8 flags: out[i] = sum of in[] over the
-// earlier elements of i's tile (SCAN_TILE elements per tile), tile_off[t] =
-// sum over the tiles before t, out[n] = the total.  The full prefix of i is
-// out[i] + tile_off[i / SCAN_TILE] (a consumer adds it, saving a pass).
+// In-place exclusive scan of ntiles tile totals by one workgroup (the
+// second step of a tiled scan); *total = their sum.  Tiles of a scan hold
+// SCAN_TILE elements.
 constexpr int SCAN_TILE = 2048;
-hipError_t launch_tile_scan_u8(const uint8_t *in, int n, int32_t *out, int32_t *tile_off,
-                               hipStream_t st);
+hipError_t launch_scan_sums(int32_t *tile_sum, int ntiles, int32_t *total, hipStream_t st);
 
 // prune.hip
 size_t prune_ws_bytes(int n, int m, bool compact);

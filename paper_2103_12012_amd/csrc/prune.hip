@@ -501,43 +501,49 @@ __device__ __forceinline__ T wave_max(T x) {
   return x;
 }
 
-// Thread per list: queue the lists to order (two atomics per workgroup pass).
+// CLS_K lists per thread and pass: queue the lists to order.  A pass
+// reserves its queue runs with one atomic per queue, so the whole grid
+// takes a few hundred atomics on the two counters instead of one pair per
+// 1024 lists.
 constexpr int CLS_BS = 1024;
+constexpr int CLS_K = 8;
+static_assert(CLS_BS * CLS_K < (1 << 16), "two 16-bit counts in one scan");
 __global__ __launch_bounds__(CLS_BS) void k_tb_sort_class(TbArgs a) {
-  __shared__ int s_cnt[2][CLS_BS / WAVE];
+  __shared__ int s_ws[CLS_BS / WAVE + 1];
   __shared__ int s_base[2];
   if (*a.status) return;
-  const int lane = lane_id();
-  const int wid = threadIdx.x / WAVE;
+  const int tid = threadIdx.x;
   const int n2 = 2 * a.n;
-  for (int i0 = blockIdx.x * CLS_BS; i0 < n2; i0 += gridDim.x * CLS_BS) {
-    const int i = i0 + threadIdx.x;
-    int len = 0;
-    if (i < n2) len = i < a.n ? a.row_ptr[i + 1] - a.row_ptr[i] : clen(a, i - a.n);
-    const bool srt = sorted_len(len);
-    const bool longl = srt && len > SORT_WAVE;
-    const unsigned long long bs = __ballot(srt && !longl), bl = __ballot(longl);
-    if (lane == 0) {
-      s_cnt[0][wid] = __popcll(bs);
-      s_cnt[1][wid] = __popcll(bl);
+  constexpr int SPAN = CLS_BS * CLS_K;
+  for (int i0 = blockIdx.x * SPAN; i0 < n2; i0 += gridDim.x * SPAN) {
+    uint32_t cls = 0;  // 2 bits per list: 1 = short queue, 2 = long queue
+    int cnt = 0;       // short count | long count << 16
+#pragma unroll
+    for (int k = 0; k < CLS_K; k++) {
+      const int i = i0 + k * CLS_BS + tid;
+      if (i >= n2) continue;
+      const int len = i < a.n ? a.row_ptr[i + 1] - a.row_ptr[i] : clen(a, i - a.n);
+      const uint32_t c = sorted_len(len) ? (len > SORT_WAVE ? 2u : 1u) : 0u;
+      cls |= c << (2 * k);
+      cnt += c == 1u ? 1 : (c == 2u ? 1 << 16 : 0);
+      a.lmeta[i] = make_int2(0, -1);  // unordered unless ordered below
+    }
+    int tot;
+    const int pre = block_excl_scan1<CLS_BS>(cnt, s_ws, &tot);
+    if (tid < 2) {
+      const int t = tid ? tot >> 16 : tot & 0xFFFF;
+      s_base[tid] = t ? atomicAdd(&a.tickets[TK_SORT_SHORT + tid], t) : 0;
     }
     __syncthreads();
-    if (threadIdx.x < 2) {
-      int tot = 0;
-      for (int w = 0; w < CLS_BS / WAVE; w++) tot += s_cnt[threadIdx.x][w];
-      s_base[threadIdx.x] = tot ? atomicAdd(&a.tickets[TK_SORT_SHORT + threadIdx.x], tot) : 0;
+    int offs = s_base[0] + (pre & 0xFFFF), offl = s_base[1] + (pre >> 16);
+#pragma unroll
+    for (int k = 0; k < CLS_K; k++) {
+      const uint32_t c = (cls >> (2 * k)) & 3u;
+      const int i = i0 + k * CLS_BS + tid;
+      if (c == 1u) a.sl[offs++] = i;
+      else if (c == 2u) a.sl[n2 - 1 - offl++] = i;
     }
-    __syncthreads();
-    int offs = s_base[0], offl = s_base[1];
-    for (int w = 0; w < wid; w++) {
-      offs += s_cnt[0][w];
-      offl += s_cnt[1][w];
-    }
-    const unsigned long long below = (1ull << lane) - 1ull;
-    if (srt && !longl) a.sl[offs + __popcll(bs & below)] = i;
-    if (longl) a.sl[n2 - 1 - (offl + __popcll(bl & below))] = i;
-    if (i < n2) a.lmeta[i] = make_int2(0, -1);  // unordered unless ordered below
-    __syncthreads();
+    __syncthreads();  // s_ws and s_base are reused by the next pass
   }
 }
 
@@ -718,75 +724,83 @@ __device__ __forceinline__ int owner_len(const TbArgs &a, int i) {
   return a.row_ptr[u + 1] - a.row_ptr[u];
 }
 
-// Tier of every owner.  Light owners with work are appended to llist;
-// heavy owners to their tier's list with their items (about HV_TARGET
-// estimated probes each, at least ITEM_MINQ arcs), slots and item ranges
-// reserved with one atomic per workgroup pass and tier; an owner with a
-// global table reserves its slots.
+// Tier of every owner, CLF_K owners per thread and pass.  Light owners with
+// work are appended to llist; heavy owners to their tier's list with their
+// items (about HV_TARGET estimated probes each, at least ITEM_MINQ arcs),
+// slots and item ranges reserved with one atomic per pass and tier; an
+// owner with a global table reserves its slots.
 constexpr int CLF_BS = 1024;
+constexpr int CLF_K = 4;
 __global__ __launch_bounds__(CLF_BS) void k_tb_classify(TbArgs a) {
-  __shared__ int s_cnt[CLF_BS / WAVE];
+  __shared__ int s_ws[CLF_BS / WAVE + 1];
   __shared__ int s_base;
   __shared__ int s_h[2 * NTIER];  // owners and items per tier, then their bases
   if (*a.status) return;
-  const int lane = lane_id();
-  const int wid = threadIdx.x / WAVE;
+  const int tid = threadIdx.x;
   const int n2 = 2 * a.n;
-  for (int i0 = blockIdx.x * CLF_BS; i0 < n2; i0 += gridDim.x * CLF_BS) {
-    if (threadIdx.x < 2 * NTIER) s_h[threadIdx.x] = 0;
-    const int i = i0 + threadIdx.x;
-    const bool in = i < n2;
-    const int wk = in ? a.work[i] : 0;
-    const int len = in ? owner_len(a, i) : 0;
-    const bool heavy = wk > 0 && (len > LT_DEG || wk > LT_WORK);
-    const bool light = wk > 0 && !heavy;
-    const int tier = len > HM_TCAP ? T_BIG : (len > HM1_TCAP ? 2 : (len > HS_TCAP ? 1 : 0));
-    int items = 0;
-    if (heavy) {
-      const int cap = len / ITEM_MINQ > 1 ? len / ITEM_MINQ : 1;
-      const long long tgt = tier == T_BIG ? HV_TARGET_BIG : HV_TARGET;
-      const long long want = ((long long)wk + tgt - 1) / tgt;
-      items = want < 1 ? 1 : (want > cap ? cap : (int)want);
-    }
-    const unsigned long long bl = __ballot(light);
-    if (lane == 0) s_cnt[wid] = __popcll(bl);
+  constexpr int SPAN = CLF_BS * CLF_K;
+  for (int i0 = blockIdx.x * SPAN; i0 < n2; i0 += gridDim.x * SPAN) {
+    if (tid < 2 * NTIER) s_h[tid] = 0;
     __syncthreads();
-    int jl = 0, ol = 0;
-    if (heavy) {
-      jl = atomicAdd(&s_h[tier], 1);
-      ol = atomicAdd(&s_h[NTIER + tier], items);
-    }
-    if (threadIdx.x == 0) {
-      int tot = 0;
-      for (int w = 0; w < CLF_BS / WAVE; w++) tot += s_cnt[w];
-      s_base = tot ? atomicAdd(&a.tickets[TK_LIGHT], tot) : 0;
-    }
-    __syncthreads();
-    if (threadIdx.x < 2 * NTIER) {
-      const int v = s_h[threadIdx.x];
-      s_h[threadIdx.x] = v ? atomicAdd(&a.hc[threadIdx.x], v) : 0;
-    }
-    __syncthreads();
-    int off = s_base;
-    for (int w = 0; w < wid; w++) off += s_cnt[w];
-    if (light) a.llist[off + __popcll(bl & ((1ull << lane) - 1ull))] = i;
-    if (in) {
+    int tier[CLF_K], items[CLF_K], jl[CLF_K], ol[CLF_K];
+    uint32_t light = 0, heavy = 0;  // bit k: owner k of this thread
+    int nlight = 0;
+#pragma unroll
+    for (int k = 0; k < CLF_K; k++) {
+      const int i = i0 + k * CLF_BS + tid;
+      tier[k] = 0;
+      items[k] = 0;
+      jl[k] = 0;
+      ol[k] = 0;
+      if (i >= n2) continue;
+      const int wk = a.work[i];
+      const int len = owner_len(a, i);
+      const bool hv = wk > 0 && (len > LT_DEG || wk > LT_WORK);
+      const int tr = len > HM_TCAP ? T_BIG : (len > HM1_TCAP ? 2 : (len > HS_TCAP ? 1 : 0));
+      if (hv) {
+        const int cap = len / ITEM_MINQ > 1 ? len / ITEM_MINQ : 1;
+        const long long tgt = tr == T_BIG ? HV_TARGET_BIG : HV_TARGET;
+        const long long want = ((long long)wk + tgt - 1) / tgt;
+        items[k] = want < 1 ? 1 : (want > cap ? cap : (int)want);
+        tier[k] = tr;
+        heavy |= 1u << k;
+        jl[k] = atomicAdd(&s_h[tr], 1);
+        ol[k] = atomicAdd(&s_h[NTIER + tr], items[k]);
+      } else if (wk > 0) {
+        light |= 1u << k;
+        nlight++;
+      }
       // hflag = heavy tier + 1 (0 = light or no work)
-      a.hflag[i] = heavy ? tier + 1 : 0;
+      a.hflag[i] = hv ? tr + 1 : 0;
       int g = 0;
-      if (heavy && tier == T_BIG && len > HV_TCAP) g = (1 << tb_bits(len, 6)) / G_UNIT;
+      if (hv && tr == T_BIG && len > HV_TCAP) g = (1 << tb_bits(len, 6)) / G_UNIT;
       a.gsz[i] = g;
       if (g) a.goff[i] = atomicAdd(&a.hc[2 * NTIER], g);
     }
-    if (heavy) {
-      const HList &h = a.hl[tier];
-      const int jj = s_h[tier] + jl, o = s_h[NTIER + tier] + ol;
-      h.id[jj] = i;
-      h.items[jj] = items;
-      h.off[jj] = o;
-      for (int k = 0; k < items; k++) h.map[o + k] = jj;
+    // the scan's barrier also completes the tier counts in s_h
+    int tot;
+    const int pre = block_excl_scan1<CLF_BS>(nlight, s_ws, &tot);
+    if (tid == 0) s_base = tot ? atomicAdd(&a.tickets[TK_LIGHT], tot) : 0;
+    if (tid < 2 * NTIER) {
+      const int v = s_h[tid];
+      s_h[tid] = v ? atomicAdd(&a.hc[tid], v) : 0;
     }
     __syncthreads();
+    int off = s_base + pre;
+#pragma unroll
+    for (int k = 0; k < CLF_K; k++) {
+      const int i = i0 + k * CLF_BS + tid;
+      if (light >> k & 1u) a.llist[off++] = i;
+      if (heavy >> k & 1u) {
+        const HList &h = a.hl[tier[k]];
+        const int jj = s_h[tier[k]] + jl[k], o = s_h[NTIER + tier[k]] + ol[k];
+        h.id[jj] = i;
+        h.items[jj] = items[k];
+        h.off[jj] = o;
+        for (int q = 0; q < items[k]; q++) h.map[o + q] = jj;
+      }
+    }
+    __syncthreads();  // s_ws, s_base and s_h are reused by the next pass
   }
 }
 
@@ -1258,31 +1272,72 @@ __global__ void k_tb_count_pruned(const uint8_t *keep, int m, sssp_stats *stats,
 }
 
 // ------------------------------------------------------------ compaction
-// The kept arcs before arc e number pos[e] + toff[e / SCAN_TILE] (a tile-local
-// scan of keep plus the tile's offset; pos[m] is the kept total): kept arc
-// e goes there, and the pruned row u starts at that count for row_ptr[u]
-// (order is preserved).
-__device__ __forceinline__ int kept_before(const int32_t *pos, const int32_t *toff, int m,
-                                           int e) {
+// The kept arcs before arc e: the kept arcs of the tiles before e's tile
+// (SCAN_TILE arcs per tile; toff, a scan of the tiles' kept counts), plus
+// those of e's tile before e's 32-arc word (kpre), plus those of the word
+// before e (kbits, one bit per arc).  Kept arc e goes there, and the pruned
+// row u starts at that count for row_ptr[u] (order is preserved).
+// kpre[ceil(m/32)] holds the kept total.
+constexpr int KT_BS = 256;
+constexpr int KT_EPT = SCAN_TILE / KT_BS;
+static_assert(KT_EPT == 8, "a thread's flags are one byte of its 32-arc word");
+
+__global__ __launch_bounds__(KT_BS) void k_keep_tiles(const uint8_t *keep, int m,
+                                                      uint32_t *kbits, int32_t *kpre,
+                                                      int32_t *tile_sum) {
+  __shared__ int s_ws[KT_BS / WAVE + 1];
+  const int tid = threadIdx.x;
+  const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)tid * KT_EPT;
+  uint32_t m8 = 0;  // bit j: arc base + j is kept
+  if (base + KT_EPT <= m && (reinterpret_cast<uintptr_t>(keep) & 7u) == 0) {
+    const uint2 v = *reinterpret_cast<const uint2 *>(keep + base);
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      m8 |= ((v.x >> (8 * j)) & 0xFFu) ? 1u << j : 0u;
+      m8 |= ((v.y >> (8 * j)) & 0xFFu) ? 1u << (4 + j) : 0u;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < KT_EPT; j++)
+      if (base + j < m && keep[base + j]) m8 |= 1u << j;
+  }
+  int tot;
+  const int pre = block_excl_scan1<KT_BS>(__popc(m8), s_ws, &tot);
+  uint32_t word = m8 << (8 * (tid & 3));  // four threads make a word
+  word |= __shfl_xor(word, 1);
+  word |= __shfl_xor(word, 2);
+  if ((tid & 3) == 0 && base < m) {
+    kbits[base >> 5] = word;
+    kpre[base >> 5] = pre;
+  }
+  if (tid == 0) tile_sum[blockIdx.x] = tot;
+}
+
+__device__ __forceinline__ int kept_before(const uint32_t *kbits, const int32_t *kpre,
+                                           const int32_t *toff, int m, int e) {
   if (e <= 0) return 0;
-  return e >= m ? pos[m] : pos[e] + toff[e / SCAN_TILE];
+  if (e >= m) return kpre[((long long)m + 31) >> 5];
+  const int wi = e >> 5;
+  return toff[e / SCAN_TILE] + kpre[wi] + __popc(kbits[wi] & ((1u << (e & 31)) - 1u));
 }
 
 __global__ void k_compact(const int32_t *row_ptr, const int32_t *col, const uint32_t *w,
-                          const uint8_t *keep, int n, int m, const int32_t *pos,
-                          const int32_t *toff, int32_t *out_row_ptr, int32_t *out_col,
-                          uint32_t *out_w, int32_t *edge_map, const int32_t *status) {
+                          const uint8_t *keep, int n, int m, const uint32_t *kbits,
+                          const int32_t *kpre, const int32_t *toff, int32_t *out_row_ptr,
+                          int32_t *out_col, uint32_t *out_w, int32_t *edge_map,
+                          const int32_t *status) {
   if (*status) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int stride = gridDim.x * blockDim.x;
   for (int e = t; e < m; e += stride)
     if (keep[e]) {
-      const int p = kept_before(pos, toff, m, e);
+      const int p = kept_before(kbits, kpre, toff, m, e);
       out_col[p] = col[e];
       out_w[p] = w[e];
       edge_map[p] = e;
     }
-  for (int u = t; u <= n; u += stride) out_row_ptr[u] = kept_before(pos, toff, m, row_ptr[u]);
+  for (int u = t; u <= n; u += stride)
+    out_row_ptr[u] = kept_before(kbits, kpre, toff, m, row_ptr[u]);
 }
 
 // ------------------------------------------------------------ host side
@@ -1290,7 +1345,7 @@ namespace {
 struct PruneLayout {
   int cs, nb, ct, tiles;
   size_t src, trow, btot, bfill, bstart, stage, ccnt, cfill, cb, cyw, ceid, rs, lmeta, sl, llist, work, hflag, hl[NTIER][4], gsz,
-      goff, gkey, gval, tmp, misc, pos, total;
+      goff, gkey, gval, tmp, misc, kbits, kpre, total;
 };
 
 PruneLayout prune_layout(int n, int m, bool compact) {
@@ -1345,7 +1400,9 @@ PruneLayout prune_layout(int n, int m, bool compact) {
   const size_t scan_n = n2 + 1;
   L.tmp = take(scan_tmp_bytes((int)(scan_n > (size_t)m + 1 ? scan_n : (size_t)m + 1)));
   L.misc = take(256);
-  L.pos = compact ? take(4ull * (m + 1)) : 0;
+  const size_t nw = ((size_t)m + 31) / 32;
+  L.kbits = compact ? take(4 * nw) : 0;
+  L.kpre = compact ? take(4 * (nw + 1)) : 0;
   L.total = off;
   return L;
 }
@@ -1488,7 +1545,8 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   a.status = reinterpret_cast<int32_t *>(misc + 128);  // after 32 ticket counters
   a.hc = reinterpret_cast<int32_t *>(misc + 192);
   a.stats = stats;
-  int32_t *pos = out_row_ptr ? reinterpret_cast<int32_t *>(ws + L.pos) : nullptr;
+  uint32_t *kbits = out_row_ptr ? reinterpret_cast<uint32_t *>(ws + L.kbits) : nullptr;
+  int32_t *kpre = out_row_ptr ? reinterpret_cast<int32_t *>(ws + L.kpre) : nullptr;
   *status_out = a.status;
 
   const int blocks = 2048;
@@ -1545,11 +1603,16 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   if (ev_stop && hipEventRecord((hipEvent_t)ev_stop, st) != hipSuccess) return SSSP_ERR_HIP;
   hipLaunchKernelGGL(k_tb_count_pruned, dim3(512), dim3(256), 0, st, keep, m, stats, a.status);
   if (out_row_ptr) {
-    if (launch_tile_scan_u8(keep, m, pos, tmp, st) != hipSuccess) return SSSP_ERR_HIP;
+    const int ntiles = (int)(((long long)m + SCAN_TILE - 1) / SCAN_TILE);
+    if (ntiles > 0)
+      hipLaunchKernelGGL(k_keep_tiles, dim3(ntiles), dim3(KT_BS), 0, st, keep, m, kbits, kpre,
+                         tmp);
+    if (launch_scan_sums(tmp, ntiles, kpre + ((long long)m + 31) / 32, st) != hipSuccess)
+      return SSSP_ERR_HIP;
     hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(256), 0, st, g.row_ptr, g.col,
-                       static_cast<const uint32_t *>(g.w), keep, n, m, pos, tmp, out_row_ptr,
-                       out_col,
-                       static_cast<uint32_t *>(out_w), edge_map, a.status);
+                       static_cast<const uint32_t *>(g.w), keep, n, m, kbits, kpre, tmp,
+                       out_row_ptr, out_col, static_cast<uint32_t *>(out_w), edge_map,
+                       a.status);
   }
   hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(64), 0, st, a.status, stats);
   return hipGetLastError() == hipSuccess ? SSSP_OK : SSSP_ERR_HIP;

@@ -89,13 +89,8 @@ hipError_t launch_excl_scan(const int32_t *in, int n, int32_t *out, int32_t *tmp
   return excl_scan_t(in, n, out, tmp, st);
 }
 
-hipError_t launch_tile_scan_u8(const uint8_t *in, int n, int32_t *out, int32_t *tile_off,
-                               hipStream_t st) {
-  const int ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
-  if (ntiles > 0)
-    hipLaunchKernelGGL(k_scan_tiles<uint8_t>, dim3(ntiles), dim3(SCAN_BS), 0, st, in, n, out,
-                       tile_off);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_BS), 0, st, tile_off, ntiles, out + n);
+hipError_t launch_scan_sums(int32_t *tile_sum, int ntiles, int32_t *total, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_BS), 0, st, tile_sum, ntiles, total);
   return hipGetLastError();
 }
 
