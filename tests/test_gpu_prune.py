@@ -60,6 +60,49 @@ def test_c1_keep_mask_and_compaction():
     assert s["status"] == 0 and s["edges_pruned"] == g.m - kept.size and s["wedges"] > 0
 
 
+def test_compaction_with_unaligned_keep_buffer():
+    """The keep mask may start at any byte address: a mask one byte past an
+    aligned address, over an arc count that is not a multiple of 8, 32 or
+    the 2048-arc scan tile, gives the oracle's keep mask and compaction, and
+    nothing is written outside it."""
+    import ctypes
+
+    S = sssp_mod()
+    g = gen.uniform(5000, 41003, seed=21)
+    assert g.m % 8 and g.m % 32 and g.m % 2048
+    rp, c, w = dev(g)
+    L = S.lib()
+    gc = S._csr(rp, c, w)
+    o = S.make_opts(num_partitions=4, validate=False)
+    buf = torch.zeros(g.m + 16, dtype=torch.uint8, device="cuda")
+    keep = buf[1:1 + g.m]
+    prp = torch.empty(g.n + 1, dtype=torch.int32, device="cuda")
+    pc = torch.empty(g.m, dtype=torch.int32, device="cuda")
+    pw = torch.empty(g.m, dtype=torch.int32, device="cuda")
+    em = torch.empty(g.m, dtype=torch.int32, device="cuda")
+    outs = [S._ptr(t) for t in (prp, pc, pw, em)]
+    nb = ctypes.c_size_t(0)
+    assert L.sssp_prune(ctypes.byref(gc), ctypes.byref(o), None, *outs, None, None,
+                        ctypes.byref(nb), None) == 0
+    ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    n2 = ctypes.c_size_t(ws.numel())
+    assert L.sssp_prune(ctypes.byref(gc), ctypes.byref(o), S._ptr(keep), *outs, None,
+                        S._ptr(ws), ctypes.byref(n2), S._stream()) == 0
+    torch.cuda.synchronize()
+    ref = oracle.trishla(g.row_ptr, g.col, g.w)
+    assert np.array_equal(keep.cpu().numpy(), ref)
+    kept = np.nonzero(ref)[0]
+    k = kept.size
+    assert 0 < k < g.m
+    assert np.array_equal(em[:k].cpu().numpy(), kept)
+    assert np.array_equal(pc[:k].cpu().numpy(), g.col[kept])
+    assert np.array_equal(pw[:k].cpu().numpy().view(np.uint32), g.w[kept])
+    cnt = np.bincount(g.src()[kept], minlength=g.n)
+    assert np.array_equal(prp.cpu().numpy(), np.concatenate([[0], np.cumsum(cnt)]))
+    b = buf.cpu().numpy()
+    assert b[0] == 0 and not b[1 + g.m:].any()
+
+
 @pytest.mark.parametrize("scale,seed", [(10, 11), (13, 12), (16, 13)])
 def test_rmat_keep_mask(scale, seed):
     g = gen.rmat(scale, seed)
