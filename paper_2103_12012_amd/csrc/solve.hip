@@ -252,7 +252,8 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
   __shared__ uint32_t s_d[FCAP];      // gather: listed distances; relax: frontier distances
   __shared__ int32_t s_rs[FCAP];      // gather: listed vertices;  relax: first arc of each
   __shared__ int32_t s_off[FCAP + 1]; // relax: degree prefix
-  __shared__ uint32_t s_fm[MAXB / 32]; // gather: far mask per inbox word
+  __shared__ uint32_t s_fm[MAXB / 32 + 1];  // gather: far mask per inbox word (a block
+                                            // not starting on a word spans one more)
   __shared__ int s_ws[NW + 1];
   __shared__ unsigned long long s_red[NW];
   __shared__ SolveDesc s_desc;

@@ -234,10 +234,11 @@ def test_hub_floods_frontier_capacity():
 def test_largest_partition_block():
     """P = 1 on a graph of 140000 vertices is raised so that no block exceeds
     65536 vertices (the LDS dedupe bitmap and gather mask of a partition);
-    blocks of exactly 65536 vertices (P = 2 on 131072) fill both; the
-    results are exact."""
+    blocks of exactly 65536 vertices (P = 2 on 131072) fill both, and blocks
+    of 65535 (P = 2 on 131069) put the second block's 65535 vertices over
+    2049 inbox words; the results are exact."""
     S = sssp_mod()
-    for n, P, want in ((140000, 1, 3), (131072, 2, 2)):
+    for n, P, want in ((140000, 1, 3), (131072, 2, 2), (131069, 2, 2)):
         g = gen.uniform(n, 4 * n, seed=8)
         rp, c, w = dev(g)
         solver = S.Solver(rp, c, w, num_partitions=P, stats=True)
