@@ -66,9 +66,15 @@ const char *sssp_strerror(int code);
 /* ------------------------------------------------------------ the graph */
 enum { SSSP_W_U32 = 0, SSSP_W_F32 = 1 };
 
+/* Largest graphs accepted (else SSSP_ERR_ARG): 32-bit vertex and arc
+ * indices, with room for twice the vertex count and for grid-stride steps
+ * without integer overflow in the kernels. */
+#define SSSP_N_MAX ((1 << 30) - (1 << 24))
+#define SSSP_M_MAX (0x7FFFFFFF - (1 << 24) + 1)
+
 typedef struct {
-  int32_t n;              /* number of vertices, n >= 1                    */
-  int32_t m;              /* number of arcs, 0 <= m <= 2^31 - 2            */
+  int32_t n;              /* number of vertices, 1 <= n <= SSSP_N_MAX      */
+  int32_t m;              /* number of arcs, 0 <= m <= SSSP_M_MAX          */
   const int32_t *row_ptr; /* device int32[n+1]: row_ptr[0] = 0, nondecreasing,
                              row_ptr[n] = m; arcs of u are row_ptr[u]..row_ptr[u+1]-1 */
   const int32_t *col;     /* device int32[m]: head of every arc, in [0, n)  */

@@ -55,7 +55,9 @@ DevInfo device_info() {
 // ---------------------------------------------------------------- checks
 int check_csr(const sssp_csr *g) {
   if (!g) return SSSP_ERR_ARG;
-  if (g->n < 1 || g->m < 0 || g->m > 0x7FFFFFFE) return SSSP_ERR_ARG;
+  // 32-bit vertex and arc indices: n and m leave room for 2n and for the
+  // kernels' grid-stride steps (below 2^24) without overflowing an int
+  if (g->n < 1 || g->n > SSSP_N_MAX || g->m < 0 || g->m > SSSP_M_MAX) return SSSP_ERR_ARG;
   if (!g->row_ptr) return SSSP_ERR_ARG;
   if (g->m > 0 && (!g->col || !g->w)) return SSSP_ERR_ARG;
   if (g->wtype != SSSP_W_U32 && g->wtype != SSSP_W_F32) return SSSP_ERR_ARG;

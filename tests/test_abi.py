@@ -60,6 +60,10 @@ def test_solve_host_errors(lib):
     assert ws_query(lib, fake_csr())[0] == 0
     assert ws_query(lib, fake_csr(n=0))[0] == -1
     assert ws_query(lib, fake_csr(m=-1))[0] == -1
+    assert ws_query(lib, fake_csr(m=2**31 - 2**24))[0] == 0  # SSSP_M_MAX
+    assert ws_query(lib, fake_csr(m=2**31 - 2**24 + 1))[0] == -1
+    assert ws_query(lib, fake_csr(n=2**30 - 2**24))[0] == 0  # SSSP_N_MAX
+    assert ws_query(lib, fake_csr(n=2**30 - 2**24 + 1))[0] == -1
     assert ws_query(lib, fake_csr(wtype=5))[0] == -1
     g = fake_csr()
     g.row_ptr = None
