@@ -46,7 +46,6 @@
 namespace sssp_impl {
 
 constexpr int TB_BS = 1024;
-constexpr int TB_NW = TB_BS / WAVE;
 constexpr int LT_DEG = 128;          // light owner: list length
 constexpr int LT_SLOTS = 256;        // light owner: wave-private hash slots
 constexpr int LT_WORK = 8192;        // light owner: probes

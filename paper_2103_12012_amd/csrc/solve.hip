@@ -257,7 +257,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
   __shared__ int s_ws[NW + 1];
   __shared__ unsigned long long s_red[NW];
   __shared__ SolveDesc s_desc;
-  __shared__ int s_unit, s_solve, s_exit, s_nlist, s_cnt, s_claimed, s_push, s_idle, s_stay;
+  __shared__ int s_unit, s_solve, s_exit, s_nlist, s_cnt, s_idle, s_stay;
   __shared__ unsigned long long s_far, s_lmin, s_gmin;
   __shared__ unsigned int s_upd, s_cross, s_new;
   __shared__ int32_t s_nv[FCAP];           // next round's frontier (same bucket)
@@ -429,10 +429,8 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
       st_rlx(&unit_min[unit], LABEL_INF);
       s_nlist = 0;
       s_cnt = 0;
-      s_claimed = 0;
       s_far = ~0ull;
       s_lmin = ~0ull;
-      s_push = 0;
       s_upd = 0;
       s_cross = 0;
       s_new = 0;
