@@ -402,3 +402,241 @@ def test_grad_matches_finite_differences(orc):
     assert valid.mean() > 0.95
     np.testing.assert_allclose(fd[valid], gw[valid], atol=1e-6, rtol=1e-6)
     assert np.abs(gw).sum() > 0
+
+
+# ----------------------------------------------- floating-point pins (fp32 / f64)
+#
+# The fp32 path sums costs left to right from the source in float32 (a
+# rounding step per arc), and its predecessor rule compares in float32.  The
+# brute force below enumerates simple paths in pure Python and folds each
+# path's costs in the requested numpy dtype, one rounding per arc; with
+# positive costs the least fold over simple paths equals the least over all
+# walks (a cycle never lowers a fold), which is the shortest-path value.
+
+def brute_paths_fp(g, w, s, dtype):
+    """Least left-fold (in ``dtype``) over all simple s->v paths, or None."""
+    best = [None] * g.n
+    best[s] = dtype(0)
+    rp, col = g.row_ptr.tolist(), g.col.tolist()
+    wl = [dtype(x) for x in w]
+
+    def dfs(u, d, seen):
+        for e in range(rp[u], rp[u + 1]):
+            v = col[e]
+            if v in seen:
+                continue
+            nd = dtype(d + wl[e])
+            if best[v] is None or nd < best[v]:
+                best[v] = nd
+            dfs(v, nd, seen | {v})
+
+    dfs(s, dtype(0), {s})
+    return best
+
+
+def check_fp_pred(g, w, s, dist, pe, dtype, bp):
+    """Every reached v != s has a tight predecessor arc in ``dtype``
+    arithmetic (tail's brute distance + cost == v's brute distance), its
+    tree path folds to the brute distance, and no smaller arc id into v is
+    tight; unreached vertices have none."""
+    src = g.src()
+    wl = [dtype(x) for x in w]
+    for v in range(g.n):
+        if bp[v] is None:
+            assert pe[v] == -1 and np.isinf(dist[v])
+            continue
+        assert dist[v] == bp[v]
+        if v == s:
+            assert pe[v] == -1
+            continue
+        e = int(pe[v])
+        assert e >= 0 and g.col[e] == v, (v, e)
+        u = int(src[e])
+        assert bp[u] is not None and dtype(bp[u] + wl[e]) == bp[v]
+        for e2 in range(g.m):
+            if g.col[e2] == v and e2 < e and bp[int(src[e2])] is not None:
+                assert dtype(bp[int(src[e2])] + wl[e2]) > bp[v], (v, e2, e)
+        # walk the tree back to s, then fold forward in dtype
+        path, x = [], v
+        while x != s:
+            path.append(int(pe[x]))
+            x = int(src[pe[x]])
+            assert len(path) <= g.n
+        acc = dtype(0)
+        for a in reversed(path):
+            acc = dtype(acc + wl[a])
+        assert acc == bp[v]
+
+
+@pytest.mark.parametrize("seed", range(120))
+def test_pred_f32_ties_against_path_enumeration(orc, seed):
+    # costs from {0.25, 0.5, 0.75}: sums are exact and ties are frequent, so
+    # the smallest-id rule among several tight arcs is exercised
+    g = tiny_graph(8000 + seed, n=int(2 + seed % 7), m=int(3 * (2 + seed % 7)), zero=False)
+    rng = np.random.default_rng(seed)
+    w = rng.choice(np.array([0.25, 0.5, 0.75], np.float32), size=g.m)
+    s = seed % g.n
+    dist, pred, pe = orc.solve(g.row_ptr, g.col, w, s)
+    check_fp_pred(g, w, s, dist, pe, np.float32, brute_paths_fp(g, w, s, np.float32))
+    src = g.src()
+    assert np.array_equal(pred[pe >= 0], src[pe[pe >= 0]])
+    assert np.all(pred[pe < 0] == -1)
+
+
+@pytest.mark.parametrize("seed", range(120))
+def test_pred_f32_rounding_against_path_enumeration(orc, seed):
+    # costs whose sums round in float32 (a distance offset of 2^20 in front
+    # of the tiny graph makes almost every sum inexact): a tight arc is
+    # decided in float32, so a predecessor test made in double finds no
+    # tight arc for most vertices and fails here
+    rng = np.random.default_rng(100 + seed)
+    n = int(3 + seed % 6)
+    g0 = tiny_graph(9000 + seed, n=n, m=4 * n, zero=False)
+    # vertex n is a new source joined to every vertex by an arc of cost
+    # ~2^20, so every distance is large and its sums round
+    u = np.concatenate([g0.src(), np.full(n, n)])
+    v = np.concatenate([g0.col, np.arange(n)])
+    w0 = rng.uniform(0.1, 10.0, size=g0.m).astype(np.float32)
+    big = (2.0**20 + rng.uniform(0, 64, size=n)).astype(np.float32)
+    g = gen.from_arcs(n + 1, u, v, np.concatenate([w0, big]).astype(np.float32))
+    w = g.w
+    s = n
+    dist, pred, pe = orc.solve(g.row_ptr, g.col, w, s)
+    check_fp_pred(g, w, s, dist, pe, np.float32, brute_paths_fp(g, w, s, np.float32))
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_sssp_and_pred_f64_against_path_enumeration(orc, seed):
+    rng = np.random.default_rng(300 + seed)
+    g = tiny_graph(9500 + seed, n=int(2 + seed % 7), m=int(4 * (2 + seed % 7)), zero=False)
+    # half the cases with exact ties (multiples of 1/4), half with rounding
+    if seed % 2:
+        w = rng.choice(np.array([0.25, 0.5, 0.75, 1.0]), size=g.m).astype(np.float64)
+    else:
+        w = (1e15 * rng.uniform(0.5, 1.5, size=g.m)).astype(np.float64) / 3.0
+    s = seed % g.n
+    d = orc.sssp(g.row_ptr, g.col, w, s)
+    pe, pv = orc.pred(g.row_ptr, g.col, w, s, d)
+    check_fp_pred(g, w, s, d, pe, np.float64, brute_paths_fp(g, w, s, np.float64))
+
+
+def test_sssp_f64_matches_scipy(orc):
+    # a library Dijkstra in float64: same left fold, so bit-identical
+    g = gen.rmat(12, 12, weight="f32", wlo=0.5, whi=1.5)
+    w = g.w.astype(np.float64) * (1.0 + 1.0 / 3.0)  # sums that round in float64
+    a = sp.csr_matrix((w, g.col, g.row_ptr), shape=(g.n, g.n))
+    for s in gen.random_sources(g, 3, 12):
+        ref = scipy_dijkstra(a, directed=True, indices=int(s))
+        d = orc.sssp(g.row_ptr, g.col, w, int(s))
+        assert np.array_equal(np.isfinite(ref), np.isfinite(d))
+        fin = np.isfinite(ref)
+        assert np.array_equal(ref[fin].view(np.uint64), d[fin].view(np.uint64))
+
+
+def test_certificate_f32_rejects_mutations(orc):
+    g = gen.rmat(9, 9)
+    rng = np.random.default_rng(9)
+    w = rng.choice(np.array([0.25, 0.5, 0.75, 1.0], np.float32), size=g.m)
+    s = int(np.argmax(g.out_degree()))
+    dist, pred, pe = orc.solve(g.row_ptr, g.col, w, s)
+    assert orc.certify(g.row_ptr, g.col, w, s, dist, pe) == (0, -1)
+    reached = np.nonzero(np.isfinite(dist) & (np.arange(g.n) != s))[0]
+    v = int(reached[len(reached) // 2])
+    up = np.float32(np.inf)
+    for bad_v in (np.nextafter(dist[v], np.float32(0)), np.nextafter(dist[v], up), up):
+        bad = dist.copy()
+        bad[v] = bad_v
+        assert orc.certify(g.row_ptr, g.col, w, s, bad, pe)[0] != 0
+    bad = dist.copy()
+    bad[s] = np.float32(0.25)
+    assert orc.certify(g.row_ptr, g.col, w, s, bad, pe)[0] == 1
+    bp = pe.copy(); bp[v] = (bp[v] + 1) % g.m
+    assert orc.certify(g.row_ptr, g.col, w, s, dist, bp)[0] != 0
+    bp = pe.copy(); bp[v] = -1
+    assert orc.certify(g.row_ptr, g.col, w, s, dist, bp)[0] == 4
+    # an unreached vertex given a predecessor
+    unreached = np.nonzero(~np.isfinite(dist))[0]
+    if unreached.size:
+        bp = pe.copy(); bp[int(unreached[0])] = 0
+        assert orc.certify(g.row_ptr, g.col, w, s, dist, bp)[0] == 3
+    # a larger tight arc than the smallest one
+    src = g.src()
+    tight = np.isfinite(dist[src]) & ((dist[src] + w).astype(np.float32) == dist[g.col])
+    tight &= g.col != s
+    cnt = np.bincount(g.col[tight], minlength=g.n)
+    x = int(np.nonzero(cnt > 1)[0][0])
+    last = int(np.nonzero(tight & (g.col == x))[0][-1])
+    bp = pe.copy(); bp[x] = last
+    assert orc.certify(g.row_ptr, g.col, w, s, dist, bp)[0] == 6
+    # a cycle of zero-cost arcs below the true parents
+    gc = gen.from_arcs(3, [0, 0, 1, 2], [1, 2, 2, 1])
+    wc = np.array([1, 1, 0, 0], np.float32)
+    assert orc.certify(gc.row_ptr, gc.col, wc, 0, np.array([0, 1, 1], np.float32),
+                       np.array([-1, 3, 2], np.int32))[0] in (6, 7)
+    assert orc.certify(gc.row_ptr, gc.col, wc, 0, np.array([0, 1, 1], np.float32),
+                       np.array([-1, 0, 1], np.int32)) == (0, -1)
+
+
+# Trishla with fp32 costs compares w1 + w2 < W exactly (real numbers).  The
+# cases below need more than float32 (the float sum rounds) or more than the
+# double sum (the exponents are more than 29 bits apart, so the double sum
+# rounds too and the exact remainder decides).
+
+F32_EDGE_COSTS = np.array([
+    1.0, 2.0**-60, 2.0**-61, 1.0 + 2.0**-23, 1.0 + 2.0**-22, 2.0**-24 + 2.0**-30,
+    2.0**-24, 2.0**-23, 0.5, 0.5 + 2.0**-24, 3.0, 2.0, 1.5,
+], np.float32)
+
+
+def trishla_exact(g, w):
+    """Keep mask from exact rational arithmetic (pure Python)."""
+    from fractions import Fraction
+
+    src = g.src().tolist()
+    col = g.col.tolist()
+    fw = [Fraction(float(x)) for x in w]
+    arcs = {}
+    for e in range(g.m):
+        arcs.setdefault((src[e], col[e]), []).append(fw[e])
+    keep = np.ones(g.m, np.uint8)
+    for e in range(g.m):
+        a, b = src[e], col[e]
+        for y in range(g.n):
+            if y in (a, b) or (a, y) not in arcs or (y, b) not in arcs:
+                continue
+            if min(arcs[(a, y)]) + min(arcs[(y, b)]) < fw[e]:
+                keep[e] = 0
+                break
+    return keep
+
+
+def test_trishla_f32_inexact_sums_hand_cases(orc):
+    g = gen.from_arcs(3, [0, 0, 1], [1, 2, 2])  # e0 = 0->1, e1 = 0->2, e2 = 1->2
+    one_up = np.nextafter(np.float32(1), np.float32(2))
+    cases = [
+        # (w(0->1), w(0->2), w(1->2), keep of 0->2)
+        (1.0, 1.0, 2.0**-60, 1),     # 1 + 2^-60 > 1: the double sum rounds to 1
+        (1.0, one_up, 2.0**-60, 0),  # 1 + 2^-60 < 1 + 2^-23
+        (2.0**-60, 1.0, 1.0, 1),     # operands swapped
+        (2.0**-61, 2.0**-60, 2.0**-61, 1),  # exact tie: strict comparison keeps
+        (1.0, one_up, 2.0**-24 + 2.0**-30, 0),  # float32 sum rounds up to W
+        (1.0, 1.0 + 2.0**-22, 2.0**-23 + 2.0**-24, 0),
+        (1.0, one_up, 2.0**-23, 1),  # exact tie at the ulp
+    ]
+    for w1, W, w2, expect in cases:
+        w = np.array([w1, W, w2], np.float32)
+        ref = trishla_exact(g, w)
+        assert ref[1] == expect, (w1, W, w2)
+        for method in ("brute", "mark"):
+            assert orc.trishla(g.row_ptr, g.col, w, method=method).tolist() == ref.tolist(), \
+                (method, w1, W, w2)
+
+
+@pytest.mark.parametrize("seed", range(80))
+def test_trishla_f32_matches_exact_arithmetic(orc, seed):
+    g = tiny_graph(11000 + seed, n=int(3 + seed % 8), m=int(5 * (3 + seed % 8)), loops=False)
+    rng = np.random.default_rng(seed)
+    w = rng.choice(F32_EDGE_COSTS, size=g.m)
+    ref = trishla_exact(g, w)
+    for method in ("brute", "mark"):
+        assert np.array_equal(orc.trishla(g.row_ptr, g.col, w, method=method), ref), method
