@@ -51,8 +51,10 @@ enum {
   SSSP_ERR_UNSORTED = -4,     /* sssp_prune: a row is not sorted by column */
   SSSP_ERR_WEIGHT = -5,       /* fp32 weight negative, -0.0, NaN or inf    */
   SSSP_ERR_ZERO_WEIGHT = -6,  /* sssp_backward: a weight equal to zero     */
-  SSSP_ERR_OVERFLOW = -7,     /* an integer path sum reached 2^32 - 1, or an
-                                 fp32 path sum overflowed to +inf          */
+  SSSP_ERR_OVERFLOW = -7,     /* a final distance does not fit: an integer
+                                 distance reaches 2^32 - 1, or a reachable
+                                 vertex's fp32 distance is +inf.  A longer
+                                 path whose sum does not fit is no error    */
   SSSP_ERR_TIMEOUT = -8,      /* max_rounds or the time limit was reached  */
   SSSP_ERR_WORKSPACE = -9,    /* workspace missing, too small or misaligned */
   SSSP_ERR_HIP = -10,         /* a HIP runtime call failed                 */
@@ -151,8 +153,14 @@ typedef struct {
  * w1 + w2 < W (strict; integer sums in 64 bits, fp32 sums compared exactly).
  * All arcs are tested against the input graph at once.  Scope GLOBAL
  * (default) allows any y; SSSP_F_PRUNE_LOCAL requires y to lie in u's 1D
- * partition (Sec. III-A).  Deleting such arcs never changes a distance nor
- * the predecessor rule's choice (a deleted arc is never tight).
+ * partition (Sec. III-A).  With integer costs, deleting such arcs never
+ * changes a distance nor the predecessor rule's choice (a deleted arc is
+ * never tight).  With fp32 costs the same holds for exact sums; the solve,
+ * however, rounds every fp32 sum, so on a pruned fp32 graph a rounded
+ * distance may come out a few ulps different (e.g. d(u) = 2^24 + 2,
+ * w1 = 1, w2 = 1.5, W = 2.9: the arc of cost W is deleted because
+ * 2.5 < 2.9, but fl(fl(d(u) + 1) + 1.5) = 2^24 + 6 > fl(d(u) + 2.9) =
+ * 2^24 + 4).
  *
  * Requires every row sorted by column (nondecreasing).
  *   keep            device uint8[m]: 1 = kept, 0 = deleted              (out)
@@ -182,7 +190,11 @@ int sssp_prune(const sssp_csr *g, const sssp_opts *o, uint8_t *keep,
  * owner's inbox -- the asynchronous Bellman-Ford exchange between
  * partitions.  A device-wide count of pending work replaces the paper's
  * termination detection (Sec. III-D): the solve ends when it reaches zero.
- * The result does not depend on delta, P, the grid or the schedule.
+ * The result does not depend on delta, P, the grid or the schedule.  A
+ * relaxation candidate that does not fit the distance type is skipped;
+ * after the solve, SSSP_ERR_OVERFLOW is reported if and only if some final
+ * distance does not fit (an arc from a reached vertex into a vertex left
+ * unreached), which is again independent of the schedule.
  *   dist        device uint32[n] or float32[n] (per g->wtype)          (out)
  *   pred        device int32[n] or NULL                                (out)
  *   pred_edge   device int32[n] or NULL                                (out)
@@ -193,7 +205,12 @@ int sssp_solve(const sssp_csr *g, int32_t source, const sssp_opts *o,
 
 /* ---------------------------------------------------------- batched solve */
 /*
- * Many independent solves in one persistent launch.  Solve i runs on graph
+ * A project layer over sssp_solve (not a step of the paper): many
+ * independent single-source problems in one persistent launch.  Sec. IV runs
+ * the pruning once per graph and the two remaining phases once per source;
+ * this entry point runs those per-source phases of many (graph, source)
+ * pairs together, each pair's partitions being scheduling units of one
+ * shared unit space.  Solve i runs on graph
  * solve_graph[i] (an index into `graphs`) from solve_source[i] and writes
  * its n_i outputs at element offset out_offset[i] of dist / pred /
  * pred_edge.  Each solve's result equals sssp_solve on the same input.

@@ -148,7 +148,10 @@ def solve(row_ptr, col, w, source: int):
 
     Returns (dist, pred, pred_edge) with dist uint32 (0xFFFFFFFF unreached) for
     integer weights -- raising OverflowError if a distance reaches 2**32-1 --
-    or float32 (+inf unreached) for fp32 weights.
+    or float32 (+inf unreached) for fp32 weights -- raising OverflowError if a
+    vertex reachable from the source has the float32 distance +inf (its path
+    sum overflowed).  Only final distances decide: a path that overflows
+    while a shorter one exists is no error.
     """
     d = sssp(row_ptr, col, w, source)
     pe, pv = pred(row_ptr, col, w, source, d)
@@ -159,7 +162,25 @@ def solve(row_ptr, col, w, source: int):
         out = np.full(d.shape, U32_INF, dtype=np.uint32)
         out[reached] = d[reached].astype(np.uint32)
         d = out
+    elif d.dtype == np.float32 and not np.isfinite(d).all():
+        if reachable(row_ptr, col, source)[~np.isfinite(d)].any():
+            raise OverflowError("a reachable vertex has distance +inf in float32")
     return d, pv, pe
+
+
+def reachable(row_ptr, col, source: int):
+    """Vertices reachable from ``source`` (breadth-first search by scipy)."""
+    import scipy.sparse as sps
+    from scipy.sparse.csgraph import breadth_first_order
+
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    c = np.ascontiguousarray(col, dtype=np.int32)
+    n = rp.shape[0] - 1
+    a = sps.csr_matrix((np.ones(c.shape[0], dtype=np.int8), c, rp), shape=(n, n))
+    order = breadth_first_order(a, int(source), directed=True, return_predecessors=False)
+    mask = np.zeros(n, dtype=bool)
+    mask[order] = True
+    return mask
 
 
 def trishla(row_ptr, col, w, local_scope: bool = False, nparts: int = 1,

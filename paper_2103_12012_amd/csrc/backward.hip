@@ -38,8 +38,9 @@ struct BwdArgs {
   int32_t *status;
 };
 
+// Clears the gradient (and the per-vertex counters) even after a validation
+// error, so the output never holds stale memory.
 __global__ void k_bwd_zero(BwdArgs a) {
-  if (*a.status) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int stride = gridDim.x * blockDim.x;
   for (int e = t; e < a.m; e += stride) a.grad_w[e] = 0.0f;

@@ -199,7 +199,7 @@ struct Ctrl {
   uint32_t done;    // set once the solve has finished or aborted
   int32_t status;   // first device-detected error
   uint32_t nunits;
-  uint32_t pad0;
+  uint32_t ovf;     // a relaxation candidate did not fit the distance type
   unsigned long long window;  // bounded lag in dist units (DELTA_INF = none)
   uint32_t pad[26];
 };

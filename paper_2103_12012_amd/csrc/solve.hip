@@ -75,7 +75,7 @@ template <> struct Dist<SSSP_W_U32> {
                                                 unsigned long long window) {
     return d <= g + window;
   }
-  // d + w in 64 bits; overflow when it reaches the unreachable sentinel.
+  // d + w in 64 bits; a sum reaching the unreachable sentinel does not fit.
   __device__ static __forceinline__ uint32_t add(uint32_t d, uint32_t w, bool &ovf) {
     unsigned long long s = (unsigned long long)d + w;
     ovf = s >= 0xFFFFFFFFull;
@@ -96,7 +96,7 @@ template <> struct Dist<SSSP_W_F32> {
     return __uint_as_float((uint32_t)d) <=
            __uint_as_float((uint32_t)g) + __uint_as_float((uint32_t)window);
   }
-  // fl32(d + w), round to nearest even; +inf counts as overflow.
+  // fl32(d + w), round to nearest even; +inf does not fit.
   __device__ static __forceinline__ uint32_t add(uint32_t d, uint32_t w, bool &ovf) {
     float s = __uint_as_float(d) + __uint_as_float(w);
     uint32_t b = __float_as_uint(s);
@@ -146,6 +146,7 @@ __global__ void k_init_global(SolveArgs a, int nsolves) {
     a.ctrl->done = 0u;
     a.ctrl->status = 0;
     a.ctrl->nunits = (uint32_t)a.nunits;
+    a.ctrl->ovf = 0u;
     a.ctrl->window = a.window;
   }
   if (a.stats) {
@@ -677,7 +678,11 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
           bool ovf;
           nd[j] = Dist<WT>::add(du[j], wv[j], ovf);
           if (ovf) {
-            set_status(&ctrl->status, SSSP_ERR_OVERFLOW);
+            // a candidate that does not fit is no shorter path to anything
+            // that fits: skip it.  Whether a final distance overflowed is
+            // decided after the fixed point (k_overflow_check); this flag
+            // only says that the check has to look.
+            st_rlx(&ctrl->ovf, 1u);
             act[j] = false;
             continue;
           }
@@ -856,12 +861,24 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
 // --------------------------------------------------------------- epilogue
 // Unpacks labels: dist = high word (sentinel kept), pred_edge = low word
 // (-1 for none), pred = tail of pred_edge by binary search in row_ptr.
+//
+// It also decides overflow, but only when the solve met a relaxation
+// candidate that did not fit the distance type (Ctrl::ovf).  The solve
+// skipped those candidates, so its fixed point is the true distance wherever
+// that fits and +inf where the true distance is finite but too large.  Some
+// true distance is too large exactly when an arc leads from a reached vertex
+// to a vertex left at +inf (on a shortest path to such a vertex, the first
+// vertex whose distance does not fit has a reached predecessor): each thread
+// scans the rows of its reached vertices for such an arc.  Not after another
+// error, since the labels and the CSR may then be unusable.
 template <int WT>
 __global__ void k_epilogue(SolveArgs a) {
   const int s = blockIdx.y;
   const SolveDesc d = a.desc[s];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int stride = gridDim.x * blockDim.x;
+  const bool check = ld_rlx(&a.ctrl->ovf) != 0u && ld_rlx(&a.ctrl->status) == 0;
+  bool over = false;
   uint32_t *dist = static_cast<uint32_t *>(d.dist);
   for (int v = t; v < d.n; v += stride) {
     const unsigned long long lab = d.label[v];
@@ -884,13 +901,27 @@ __global__ void k_epilogue(SolveArgs a) {
           pv = l;
         }
       }
+      if (check && !over) {
+        const int r0 = d.row_ptr[v], r1 = d.row_ptr[v + 1];
+        if (r0 >= 0 && r1 >= r0 && r1 <= d.m)
+          for (int e = r0; e < r1 && !over; e++) {
+            const int x = d.col[e];
+            over = (unsigned)x < (unsigned)d.n && d.label[x] == LABEL_INF;
+          }
+      }
     }
     dist[v] = dv;
     if (d.pred) d.pred[v] = pv;
     if (d.pred_edge) d.pred_edge[v] = pe;
   }
+  if (over) {
+    set_status(&a.ctrl->status, SSSP_ERR_OVERFLOW);
+    if (a.stats) set_status(&a.stats->status, SSSP_ERR_OVERFLOW);
+  }
   if (s == 0 && t == 0 && a.stats) {
-    a.stats->status = a.ctrl->status;
+    // the stats were cleared before the solve; a block that finds an
+    // overflow sets both words, so copy only a status that is already set
+    set_status(&a.stats->status, ld_rlx(&a.ctrl->status));
     a.stats->num_partitions = d.nparts;
     a.stats->delta_bits = d.delta;
   }

@@ -369,7 +369,10 @@ def solve_batch(graphs, solve_graph, solve_source, *, sync=True, **kw):
 # ------------------------------------------------------------------ backward
 def backward(row_ptr, col, w, source: int, dist, pred_edge, grad_dist, *, validate=True,
              sync=False, events=None, ws=None):
-    """d(sum grad_dist * dist) / d w along the tree pred_edge (float32[m])."""
+    """d(sum grad_dist * dist) / d w along the tree pred_edge (float32[m]).
+    With sync=True a device-detected error raises SSSPError; the returned
+    gradient is cleared to zero before any tree work, so after an error it
+    holds zeros, never stale memory."""
     g = _csr(row_ptr, col, w)
     if g.wtype != W_F32:
         raise TypeError("backward needs float32 weights")
@@ -391,13 +394,20 @@ def backward(row_ptr, col, w, source: int, dist, pred_edge, grad_dist, *, valida
 
 
 class SSSPDist(torch.autograd.Function):
-    """dist = SSSPDist.apply(w, row_ptr, col, source); gradients flow to w."""
+    """dist = SSSPDist.apply(w, row_ptr, col, source); gradients flow to w.
+
+    Device-detected errors (an invalid or zero cost, an overflow, a time-out,
+    a predecessor cycle) raise :class:`SSSPError` from forward and backward:
+    both wait for their kernels and read the status word, except while the
+    current stream is being captured into a graph (no synchronisation is
+    allowed then; the caller checks the result)."""
 
     @staticmethod
     def forward(ctx, w, row_ptr, col, source):
         if w.dtype != torch.float32:
             raise TypeError("SSSPDist needs float32 weights")
-        dist, _, pe = solve(row_ptr, col, w, int(source), sync=False, want_pred=False)
+        sync = not torch.cuda.is_current_stream_capturing()
+        dist, _, pe = solve(row_ptr, col, w, int(source), sync=sync, want_pred=False)
         dist = dist.clone()
         pe = pe.clone()
         ctx.save_for_backward(w, row_ptr, col, dist, pe)
@@ -407,7 +417,8 @@ class SSSPDist(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_dist):
         w, row_ptr, col, dist, pe = ctx.saved_tensors
-        gw = backward(row_ptr, col, w, ctx.source, dist, pe, grad_dist)
+        sync = not torch.cuda.is_current_stream_capturing()
+        gw = backward(row_ptr, col, w, ctx.source, dist, pe, grad_dist, sync=sync)
         return gw, None, None, None
 
 

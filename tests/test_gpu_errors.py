@@ -6,8 +6,9 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 from paper_2103_12012_amd import gen
-from helpers import dev, sssp_mod
+from helpers import assert_solve_parity, dev, sssp_mod
 
 pytestmark = pytest.mark.gpu
 
@@ -67,6 +68,72 @@ def test_integer_overflow_reported():
     g = gen.from_arcs(3, [0, 1], [1, 2], np.array([0xF0000000, 0x20000000], np.uint32))
     rp, c, w = dev(g)
     assert code_of(lambda: sssp_mod().solve(rp, c, w, 0)) == -7
+    with pytest.raises(OverflowError):
+        oracle.solve(g.row_ptr, g.col, g.w, 0)
+    g = gen.from_arcs(3, [0, 1], [1, 2], np.array([0xFFFFFFFE, 1], np.uint32))
+    rp, c, w = dev(g)
+    assert code_of(lambda: sssp_mod().solve(rp, c, w, 0)) == -7
+
+
+# Overflow is decided by the final distances only: a candidate that does not
+# fit, built from a longer path or a stale label, is no error while a shorter
+# path fits (the oracle's rule).
+OVERFLOW_FREE = [
+    # 0->1 (1), 0->2 (0xFFFFFFF0), 2->1 (0x100): 2->1 overflows, 1 is reached by 0->1
+    (3, [0, 0, 2], [1, 2, 1], [1, 0xFFFFFFF0, 0x100]),
+    # an arc into the source whose candidate overflows
+    (2, [0, 1], [1, 0], [0xFFFFFFF0, 0x100]),
+    # the largest representable distance
+    (2, [0], [1], [0xFFFFFFFE]),
+    # a chain up to the limit whose next arc overflows, with a short detour
+    # to that arc's head (vertex 3 is unreachable)
+    (5, [0, 1, 2, 0], [1, 2, 4, 4], [0x7FFFFFFF, 0x7FFFFFFF, 0x10, 5]),
+]
+
+
+@pytest.mark.parametrize("case", range(len(OVERFLOW_FREE)))
+@pytest.mark.parametrize("P,delta", [(1, 0), (2, 1), (3, -1), (2, 1000)])
+def test_overflow_only_on_final_distances(case, P, delta):
+    n, u, v, w = OVERFLOW_FREE[case]
+    g = gen.from_arcs(n, u, v, np.array(w, np.uint32))
+    rp, c, wd = dev(g)
+    ref = oracle.solve(g.row_ptr, g.col, g.w, 0)
+    S = sssp_mod()
+    s = S.Solver(rp, c, wd, num_partitions=P, delta=delta, stats=True)
+    dist, pred, pe = s(0, sync=True)
+    assert s.stats.read()["status"] == 0
+    assert_solve_parity(g, 0, (dist.cpu().numpy().view(np.uint32), pred.cpu().numpy(),
+                               pe.cpu().numpy()), ref)
+
+
+def test_overflow_f32_final_distances():
+    big = np.float32(3e38)
+    g = gen.from_arcs(3, [0, 0, 2], [1, 2, 1], np.array([1.0, big, big], np.float32))
+    rp, c, w = dev(g)
+    S = sssp_mod()
+    dist, pred, pe = S.solve(rp, c, w, 0)
+    assert_solve_parity(g, 0, (dist.cpu().numpy(), pred.cpu().numpy(), pe.cpu().numpy()))
+    g = gen.from_arcs(4, [0, 1], [1, 2], np.array([big, big], np.float32))
+    rp, c, w = dev(g)
+    assert code_of(lambda: S.solve(rp, c, w, 0)) == -7
+    with pytest.raises(OverflowError):
+        oracle.solve(g.row_ptr, g.col, g.w, 0)
+
+
+def test_overflow_in_a_batch():
+    """An overflow-free graph with an overflowing candidate beside an ordinary
+    graph in one batched launch: no error, both results exact; then a batch
+    holding an overflowing solve reports it."""
+    n, u, v, w = OVERFLOW_FREE[0]
+    g0 = gen.from_arcs(n, u, v, np.array(w, np.uint32))
+    g1 = gen.rmat(10, 3)
+    S = sssp_mod()
+    dists, preds, pes = S.solve_batch([dev(g0), dev(g1)], [0, 1, 0], [0, 5, 2])
+    for (gi, src), d, p, pe in zip([(g0, 0), (g1, 5), (g0, 2)], dists, preds, pes):
+        assert_solve_parity(gi, src, (d.cpu().numpy().view(np.uint32), p.cpu().numpy(),
+                                      pe.cpu().numpy()))
+    g2 = gen.from_arcs(3, [0, 1], [1, 2], np.array([0xF0000000, 0x20000000], np.uint32))
+    assert code_of(lambda: S.solve_batch([dev(g1), dev(g2)], [0, 1], [5, 0])) == -7
 
 
 def test_sync_refused_while_capturing():
@@ -86,3 +153,36 @@ def test_sync_refused_while_capturing():
             except S.SSSPError as e:
                 err = e
     assert err is not None and err.code == -11
+
+
+@pytest.mark.parametrize("bad", [-0.0, 0.0, float("nan")])
+def test_autograd_reports_device_errors(bad):
+    """SSSPDist raises on a device-detected error: an invalid cost in the
+    forward (-0.0, NaN), a zero cost in the backward (which needs w > 0)."""
+    g = gen.rmat(8, 1, weight="f32", wlo=0.5, whi=1.5)
+    rp, c, w = dev(g)
+    s = int(gen.random_sources(g, 1, 1)[0])
+    w[int(g.row_ptr[s])] = bad
+    S = sssp_mod()
+    wt = w.clone().requires_grad_(True)
+    if bad == 0.0 and not np.signbit(bad):
+        d = S.SSSPDist.apply(wt, rp, c, s)  # zero costs are valid distances
+        with pytest.raises(S.SSSPError) as ei:
+            d[torch.isfinite(d)].sum().backward()
+        assert ei.value.code == -6
+    else:
+        with pytest.raises(S.SSSPError) as ei:
+            S.SSSPDist.apply(wt, rp, c, s)
+        assert ei.value.code == -5
+
+
+def test_backward_error_leaves_zero_gradient():
+    g = gen.rmat(8, 1, weight="f32", wlo=0.5, whi=1.5)
+    rp, c, w = dev(g)
+    S = sssp_mod()
+    s = int(gen.random_sources(g, 1, 1)[0])
+    dist, _, pe = S.solve(rp, c, w, s)
+    w[0] = 0.0
+    gw = S.backward(rp, c, w, s, dist, pe, torch.ones_like(dist))  # asynchronous
+    torch.cuda.synchronize()
+    assert bool((gw == 0).all())

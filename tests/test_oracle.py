@@ -640,3 +640,35 @@ def test_trishla_f32_matches_exact_arithmetic(orc, seed):
     ref = trishla_exact(g, w)
     for method in ("brute", "mark"):
         assert np.array_equal(orc.trishla(g.row_ptr, g.col, w, method=method), ref), method
+
+
+# ------------------------------------------------------------------ overflow
+
+def test_overflow_decided_by_final_distances(orc):
+    # a path whose sum does not fit is no error while a shorter one exists
+    g = gen.from_arcs(3, [0, 0, 2], [1, 2, 1], np.array([1, 0xFFFFFFF0, 0x100], np.uint32))
+    dist, pred, pe = orc.solve(g.row_ptr, g.col, g.w, 0)
+    assert dist.tolist() == [0, 1, 0xFFFFFFF0] and pe.tolist() == [-1, 0, 1]
+    g = gen.from_arcs(2, [0, 1], [1, 0], np.array([0xFFFFFFF0, 0x100], np.uint32))
+    assert orc.solve(g.row_ptr, g.col, g.w, 0)[0].tolist() == [0, 0xFFFFFFF0]
+    # the largest representable distance fits; one more does not
+    g = gen.from_arcs(2, [0], [1], np.array([0xFFFFFFFE], np.uint32))
+    assert orc.solve(g.row_ptr, g.col, g.w, 0)[0].tolist() == [0, 0xFFFFFFFE]
+    g = gen.from_arcs(3, [0, 1], [1, 2], np.array([0xFFFFFFFE, 1], np.uint32))
+    with pytest.raises(OverflowError):
+        orc.solve(g.row_ptr, g.col, g.w, 0)
+    g = gen.from_arcs(3, [0, 1], [1, 2], np.array([0xF0000000, 0x20000000], np.uint32))
+    with pytest.raises(OverflowError):
+        orc.solve(g.row_ptr, g.col, g.w, 0)
+
+
+def test_overflow_f32(orc):
+    big = np.float32(3e38)
+    g = gen.from_arcs(3, [0, 0, 2], [1, 2, 1])
+    dist, _, pe = orc.solve(g.row_ptr, g.col, np.array([1.0, big, big], np.float32), 0)
+    assert dist.tolist() == [0.0, 1.0, float(big)] and pe.tolist() == [-1, 0, 1]
+    g = gen.from_arcs(4, [0, 1], [1, 2])  # vertex 3 is unreachable: no error
+    with pytest.raises(OverflowError):
+        orc.solve(g.row_ptr, g.col, np.array([big, big], np.float32), 0)
+    dist, _, _ = orc.solve(g.row_ptr, g.col, np.array([1.0, 2.0], np.float32), 0)
+    assert dist.tolist() == [0.0, 1.0, 3.0, float("inf")]
