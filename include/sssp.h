@@ -59,7 +59,9 @@ enum {
   SSSP_ERR_WORKSPACE = -9,    /* workspace missing, too small or misaligned */
   SSSP_ERR_HIP = -10,         /* a HIP runtime call failed                 */
   SSSP_ERR_CAPTURE = -11,     /* SSSP_F_SYNC requested on a capturing stream */
-  SSSP_ERR_CYCLE = -12        /* sssp_backward: predecessors form a cycle  */
+  SSSP_ERR_CYCLE = -12,       /* sssp_backward: predecessors form a cycle  */
+  SSSP_ERR_TOO_LARGE = -13    /* sssp_solve_noalloc: the solve needs more than
+                                 SSSP_NOALLOC_SCRATCH_BYTES of workspace   */
 };
 
 /* Human-readable name of an error code (static string, never NULL). */
@@ -290,6 +292,26 @@ int sssp_autotune_batch(int32_t num_graphs, const sssp_csr *graphs, int32_t num_
                         const int32_t *solve_graph, const int32_t *solve_source,
                         const int64_t *out_offset, void *dist_scratch, sssp_opts *best,
                         const char *cache_path, void *ws, size_t *ws_bytes, void *stream);
+
+/* ----------------------------------------------------- solve, no allocation */
+/*
+ * For callers that cannot allocate device memory at call time (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * sssp_solve with the same arguments and results, minus the workspace.  The
+ * workspace is a fixed array of SSSP_NOALLOC_SCRATCH_BYTES inside the
+ * library, one per GPU, held from module load until the process ends.  A
+ * graph whose solve needs more (as sssp_solve's ws == NULL query reports;
+ * about 8 million vertices) is rejected with SSSP_ERR_TOO_LARGE before
+ * anything is enqueued.  The call allocates nothing; its first call on a
+ * device looks up that device's array address (hipGetSymbolAddress).  All
+ * calls on one GPU share its array: calls that overlap on one GPU (on
+ * different streams or host threads) race and must be ordered by the
+ * caller; calls in one stream are ordered already.
+ */
+#define SSSP_NOALLOC_SCRATCH_BYTES (64u << 20)
+int sssp_solve_noalloc(const sssp_csr *g, int32_t source, const sssp_opts *o,
+                       void *dist, int32_t *pred, int32_t *pred_edge,
+                       sssp_stats *stats, void *stream);
 
 /* Library version string. */
 const char *sssp_version(void);

@@ -28,6 +28,7 @@ const char *strerror_impl(int code) {
     case SSSP_ERR_HIP: return "HIP runtime error";
     case SSSP_ERR_CAPTURE: return "SSSP_F_SYNC on a capturing stream";
     case SSSP_ERR_CYCLE: return "predecessor graph has a cycle";
+    case SSSP_ERR_TOO_LARGE: return "graph too large for the library's fixed solve workspace";
     default: return "unknown error";
   }
 }

@@ -29,6 +29,7 @@ ERRORS = {
     -4: "SSSP_ERR_UNSORTED", -5: "SSSP_ERR_WEIGHT", -6: "SSSP_ERR_ZERO_WEIGHT",
     -7: "SSSP_ERR_OVERFLOW", -8: "SSSP_ERR_TIMEOUT", -9: "SSSP_ERR_WORKSPACE",
     -10: "SSSP_ERR_HIP", -11: "SSSP_ERR_CAPTURE", -12: "SSSP_ERR_CYCLE",
+    -13: "SSSP_ERR_TOO_LARGE",
 }
 ERR_WORKSPACE = -9
 
@@ -93,8 +94,9 @@ def lib() -> ctypes.CDLL:
         L.sssp_autotune_batch.argtypes = [_i32, P(CSR), _i32, P(_i32), P(_i32),
                                           P(ctypes.c_int64), _vp, P(Opts), ctypes.c_char_p,
                                           _vp, _sz, _vp]
+        L.sssp_solve_noalloc.argtypes = [P(CSR), _i32, P(Opts), _vp, _vp, _vp, _vp, _vp]
         for f in ("sssp_prune", "sssp_solve", "sssp_solve_batch", "sssp_backward",
-                  "sssp_autotune", "sssp_autotune_batch"):
+                  "sssp_autotune", "sssp_autotune_batch", "sssp_solve_noalloc"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib

@@ -31,7 +31,7 @@ def test_exports_every_declared_symbol(lib):
     names = sssp.declared_symbols()
     assert set(names) >= {"sssp_prune", "sssp_solve", "sssp_solve_batch", "sssp_backward",
                           "sssp_strerror", "sssp_autotune", "sssp_autotune_batch", "sssp_opts_init",
-                          "sssp_version"}
+                          "sssp_version", "sssp_solve_noalloc"}
     for s in names:
         assert hasattr(lib, s), s
 
@@ -164,3 +164,18 @@ def test_autotune_batch_host_errors(lib):
     # no graphs
     assert lib.sssp_autotune_batch(0, ctypes.byref(g), 1, sg, ss, off, None, ctypes.byref(o),
                                    None, None, ctypes.byref(nb), None) == -1
+
+
+def test_noalloc_rejects_graphs_beyond_the_fixed_workspace(lib):
+    """sssp_solve_noalloc refuses, on the host, a graph whose solve needs more
+    than SSSP_NOALLOC_SCRATCH_BYTES (the pointers are never dereferenced)."""
+    limit = 64 << 20
+    g = fake_csr(n=9_000_000, m=100)
+    _, need = ws_query(lib, g)
+    assert need > limit
+    assert lib.sssp_solve_noalloc(ctypes.byref(g), 0, None, ctypes.c_void_p(0x4000), None,
+                                  None, None, None) == -13
+    assert lib.sssp_solve_noalloc(ctypes.byref(g), -1, None, ctypes.c_void_p(0x4000), None,
+                                  None, None, None) == -2
+    _, need = ws_query(lib, fake_csr(n=7_000_000, m=100))
+    assert need <= limit
