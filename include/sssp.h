@@ -92,7 +92,25 @@ enum {
   SSSP_F_VALIDATE = 1u << 0,     /* check CSR and weights on the device first */
   SSSP_F_SYNC = 1u << 1,         /* wait for completion, return device status  */
   SSSP_F_PRUNE_LOCAL = 1u << 2,  /* sssp_prune: LOCAL scope (witness in u's partition) */
-  SSSP_F_NO_AUTOTUNE = 1u << 3   /* never consult the autotune cache           */
+  SSSP_F_NO_AUTOTUNE = 1u << 3,  /* never consult the autotune cache           */
+  /* sssp_solve / sssp_solve_batch: buffer cross-partition label updates.  A
+     candidate label for a head in another partition is kept in a per-batch
+     LDS table that holds the least candidate per head, and each distinct
+     head is updated once, at the end of each settle round, when the table
+     is full (the overflow goes straight to HBM) and at the end of the batch
+     (the message buffering the paper names as future work, Sec. V, with
+     min-combining).  Results are the same; only the number of global
+     atomics and the timing change. */
+  SSSP_F_BUFFER_CROSS = 1u << 4,
+  /* sssp_solve / sssp_solve_batch: the paper's local rule taken literally
+     (Alg. 3): a partition settles its vertices one at a time from a binary
+     heap in LDS, least tentative distance first, pushing every improved
+     head of its own partition and sending the others to their owners'
+     inboxes, until its heap is empty (or 256 pops; the rest goes back to
+     the inbox).  delta plays no part in a batch (the lag window still
+     bounds which partitions may run).  Results are the same.  Not together
+     with SSSP_F_BUFFER_CROSS (SSSP_ERR_ARG). */
+  SSSP_F_LOCAL_HEAP = 1u << 5
 };
 
 typedef struct {

@@ -71,6 +71,7 @@ int check_opts(const sssp_opts *o) {
     return SSSP_ERR_ARG;
   if (o->num_partitions < 0 || o->num_workgroups < 0 || o->max_rounds < 0) return SSSP_ERR_ARG;
   if (std::isnan(o->delta)) return SSSP_ERR_ARG;
+  if ((o->flags & SSSP_F_LOCAL_HEAP) && (o->flags & SSSP_F_BUFFER_CROSS)) return SSSP_ERR_ARG;
   return SSSP_OK;
 }
 
@@ -166,13 +167,20 @@ SolvePlan make_plan(const sssp_csr &g, const sssp_opts &o) {
 
 // Persistent grid: the requested size (0 = per_cu workgroups per CU), capped
 // by what can be resident at block size bs.
-int plan_grid(int wtype, int bs, int want, int per_cu_default) {
+int plan_grid(int wtype, int bs, int want, int per_cu_default, int mode) {
   const DevInfo di = device_info();
-  const int per_cu = solve_max_blocks_per_cu(wtype, bs);
+  const int per_cu = solve_max_blocks_per_cu(wtype, bs, mode);
   const int resident = di.cus * per_cu;
   if (want <= 0) want = di.cus * per_cu_default;
   int grid = want < resident ? want : resident;
   return grid < 1 ? 1 : grid;
+}
+
+// Solve mode (k_solve's local rule and update path) chosen by the flags.
+int solve_mode(uint32_t flags) {
+  if (flags & SSSP_F_LOCAL_HEAP) return SOLVE_HEAP;
+  if (flags & SSSP_F_BUFFER_CROSS) return SOLVE_BUFFERED;
+  return SOLVE_BUCKETS;
 }
 
 // Workspace layout of a (batched) solve.
@@ -274,7 +282,8 @@ int run_solves(std::vector<SolveDesc> &descs, const SolveLayout &L, int nunits, 
   // k_init ran before the validation above; the solve kernel checks status.
   if (o.event_start && hipEventRecord((hipEvent_t)o.event_start, st) != hipSuccess)
     return SSSP_ERR_HIP;
-  if (launch_solve(a, wtype, bs, grid, st) != hipSuccess) return SSSP_ERR_HIP;
+  if (launch_solve(a, wtype, bs, solve_mode(o.flags), grid, st) != hipSuccess)
+    return SSSP_ERR_HIP;
   if (o.event_stop && hipEventRecord((hipEvent_t)o.event_stop, st) != hipSuccess)
     return SSSP_ERR_HIP;
   if (launch_epilogue(a, wtype, ns, max_n, st) != hipSuccess) return SSSP_ERR_HIP;
@@ -337,7 +346,7 @@ extern "C" int sssp_solve(const sssp_csr *g, int32_t source, const sssp_opts *o,
   d.nwords = (g->n + 31) / 32;
   opts.lag = pl.lag;
   return run_solves(descs, L, pl.nparts, g->wtype, pl.bs,
-                    plan_grid(g->wtype, pl.bs, pl.grid, pl.grid_per_cu),
+                    plan_grid(g->wtype, pl.bs, pl.grid, pl.grid_per_cu, solve_mode(opts.flags)),
                     opts, g, 1, stats, w, st);
 }
 
@@ -426,7 +435,7 @@ extern "C" int sssp_solve_batch(int32_t num_graphs, const sssp_csr *graphs, int3
   if (opts.wg_size) bs = opts.wg_size;
   // the grid follows the largest per-graph plan, capped by residency at bs
   if (opts.num_workgroups) grid = opts.num_workgroups;
-  grid = plan_grid(graphs[0].wtype, bs, grid, 1);
+  grid = plan_grid(graphs[0].wtype, bs, grid, 1, solve_mode(opts.flags));
   return run_solves(descs, L, (int)nunits, graphs[0].wtype, bs, grid, opts, graphs, num_graphs,
                     stats, w, st);
 }

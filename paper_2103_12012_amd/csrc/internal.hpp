@@ -17,6 +17,13 @@ constexpr unsigned long long DELTA_AUTO = 0ull;  // bucket width set on the devi
 constexpr int ABW_STRIDE = 32;                   // active-unit bitmap word stride
 constexpr int ABW_UNITS = 8;                     // units per active-unit bitmap word
 
+// How a partition settles its vertices inside a batch (k_solve's MODE).
+enum SolveMode {
+  SOLVE_BUCKETS = 0,   // delta buckets, cross-partition labels updated at once
+  SOLVE_BUFFERED = 1,  // delta buckets, cross-partition updates buffered per head
+  SOLVE_HEAP = 2       // one vertex at a time from an LDS binary heap
+};
+
 // ------------------------------------------------------------ atomics
 // Every datum that several workgroups write or read while a kernel runs is
 // accessed with agent-scope atomics: the eight XCDs have private L2 caches,

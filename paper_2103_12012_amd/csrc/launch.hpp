@@ -10,10 +10,11 @@ hipError_t launch_validate(const sssp_csr &g, int need_sorted, int need_positive
 hipError_t launch_write_desc(const DescChunk &c, SolveDesc *table, hipStream_t st);
 hipError_t launch_init(const SolveArgs &a, int nsolves, int max_n, hipStream_t st);
 hipError_t launch_auto_delta(const SolveArgs &a, int wtype, int nsolves, hipStream_t st);
-hipError_t launch_solve(const SolveArgs &a, int wtype, int bs, int grid, hipStream_t st);
+hipError_t launch_solve(const SolveArgs &a, int wtype, int bs, int mode, int grid,
+                        hipStream_t st);
 hipError_t launch_epilogue(const SolveArgs &a, int wtype, int nsolves, int max_n,
                            hipStream_t st);
-int solve_max_blocks_per_cu(int wtype, int bs);
+int solve_max_blocks_per_cu(int wtype, int bs, int mode);
 __global__ void k_copy_status(const int32_t *status, sssp_stats *stats);
 
 // scan.hip

@@ -61,7 +61,72 @@ __device__ __forceinline__ bool act_defer(int32_t *keys, uint32_t *dmin, int *nr
   }
   return false;
 }
+// Buffered cross-partition updates (solve mode SOLVE_BUFFERED): a candidate
+// label for a head in another partition is not applied at once; the batch
+// keeps the least candidate per head in an LDS table and applies each
+// distinct head once, with one atomic min.  Push-out criteria: the end of a
+// settle round once the table holds SSSP_XB_FLUSH heads (default 1: every
+// round that buffered anything; flushing only at half a table was slower,
+// grid 4096^2 79 against 69 ms), a full table (a candidate that finds no
+// slot goes straight to HBM), and the end of the batch, before the batch's
+// pending work is returned, so nothing buffered is ever invisible to
+// termination.  Arcs of one round that lead into the same head thus cost
+// one global atomic instead of one each: the paper's message buffering,
+// with min-combining.
+constexpr int XB_SLOTS = 1024;
+#ifndef SSSP_XB_FLUSH
+#define SSSP_XB_FLUSH 1
+#endif
+
+// Keeps the least packed candidate pk for head v; false when the table is
+// crowded (the caller applies the candidate directly).
+__device__ __forceinline__ bool xb_insert(int32_t *keys, unsigned long long *vals, int *nrec,
+                                          int v, unsigned long long pk) {
+  uint32_t h = ((uint32_t)v * 2654435761u) >> 22;  // 1024 slots
+  for (int probe = 0; probe < 8; probe++) {
+    const int old = atomicCAS(&keys[h], -1, v);
+    if (old == -1) atomicAdd(nrec, 1);
+    if (old == -1 || old == v) {
+      atomicMin(&vals[h], pk);
+      return true;
+    }
+    h = (h + 1) & (XB_SLOTS - 1);
+  }
+  return false;
+}
+
 constexpr int MAX_ROUNDS_PER_BATCH = 256;
+
+// Binary min-heap in LDS for the heap mode (one thread operates on it):
+// the root is the least key; children of i are 2i+1 and 2i+2.
+constexpr int HCAP = 2048;
+__device__ __forceinline__ void heap_down(unsigned long long *h, int n, int i) {
+  const unsigned long long x = h[i];
+  for (;;) {
+    int c = 2 * i + 1;
+    if (c >= n) break;
+    unsigned long long cv = h[c];
+    if (c + 1 < n && h[c + 1] < cv) {
+      c++;
+      cv = h[c];
+    }
+    if (x <= cv) break;
+    h[i] = cv;
+    i = c;
+  }
+  h[i] = x;
+}
+// Places key x at position i (the new last slot) and restores heap order.
+__device__ __forceinline__ void heap_up(unsigned long long *h, int i, unsigned long long x) {
+  while (i > 0) {
+    const int p = (i - 1) >> 1;
+    const unsigned long long pv = h[p];
+    if (pv <= x) break;
+    h[i] = pv;
+    i = p;
+  }
+  h[i] = x;
+}
 // Pending-count raise of one batch: above MAX_ROUNDS_PER_BATCH * (2^31 - 1)
 // inbox bits, and 2^50 per workgroup keeps the sum far from overflow.
 constexpr long long RAISE = 1ll << 50;
@@ -224,6 +289,63 @@ __device__ __forceinline__ uint32_t unit_unmix(uint32_t x, uint32_t key) {
   return (x * 0x0E8B2F51u) ^ key;
 }
 
+// Applies every buffered cross-partition candidate (one atomic min per
+// distinct head), marks lowered heads in their owners' inboxes and records
+// the owners' wakeups; clears the table.  Called by the whole workgroup
+// after a barrier; the caller reduces the counters and clears the count.
+template <int BS>
+__device__ __forceinline__ void xb_flush(int32_t *keys, unsigned long long *vals,
+                                         unsigned long long *label, uint32_t *dirty, int bsize,
+                                         int unit0, unsigned long long *unit_min, uint32_t *abits,
+                                         int32_t *actk, uint32_t *actd, int *actn,
+                                         unsigned int &upd, unsigned int &cross,
+                                         unsigned int &nnew) {
+  constexpr int K = XB_SLOTS / BS < 4 ? (XB_SLOTS / BS > 0 ? XB_SLOTS / BS : 1) : 4;
+  for (int i0 = 0; i0 < XB_SLOTS; i0 += BS * K) {
+    int v[K];
+    unsigned long long pk[K], cur[K];
+#pragma unroll
+    for (int j = 0; j < K; j++) {
+      const int i = i0 + j * BS + (int)threadIdx.x;
+      v[j] = i < XB_SLOTS ? keys[i] : -1;
+      if (v[j] >= 0) {
+        pk[j] = vals[i];
+        keys[i] = -1;
+        vals[i] = ~0ull;
+        cur[j] = ld_rlx(&label[v[j]]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < K; j++) {
+      if (v[j] >= 0 && pk[j] < cur[j]) cur[j] = amin(&label[v[j]], pk[j]);
+      else v[j] = -1;
+    }
+    uint32_t ob[K];
+#pragma unroll
+    for (int j = 0; j < K; j++) {
+      if (v[j] < 0) continue;
+      if ((uint32_t)(cur[j] >> 32) <= (uint32_t)(pk[j] >> 32)) {
+        v[j] = -1;
+        continue;
+      }
+      upd++;
+      cross++;
+      ob[j] = aor(&dirty[v[j] >> 5], 1u << (v[j] & 31));
+    }
+#pragma unroll
+    for (int j = 0; j < K; j++) {
+      if (v[j] < 0 || ((ob[j] >> (v[j] & 31)) & 1u)) continue;  // already pending
+      nnew++;
+      const int gu = unit0 + v[j] / bsize;
+      const uint32_t nd = (uint32_t)(pk[j] >> 32);
+      if (!act_defer(actk, actd, actn, gu, nd)) {
+        amin(&unit_min[gu], (unsigned long long)nd);
+        aor(&abits[abw(gu)], abit(gu));
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ solve
 //
 // One batch of a workgroup:
@@ -241,11 +363,13 @@ __device__ __forceinline__ uint32_t unit_unmix(uint32_t x, uint32_t key) {
 #ifndef SSSP_SOLVE_MIN_WAVES
 #define SSSP_SOLVE_MIN_WAVES 2
 #endif
-template <int WT, int BS>
+template <int WT, int BS, int MODE>
 __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_solve(SolveArgs a) {
   constexpr int NW = BS / WAVE;
   constexpr int U = 4;  // arcs per thread per round
   constexpr int EPT = FCAP / BS;
+  constexpr bool XBUF = MODE == SOLVE_BUFFERED;
+  constexpr bool HEAP = MODE == SOLVE_HEAP;
   static_assert(FCAP % BS == 0, "FCAP must be a multiple of the block size");
 
   __shared__ int32_t s_v[FCAP];       // claimed frontier vertices
@@ -268,8 +392,21 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
   __shared__ int32_t s_actk[ACT_SLOTS];   // deferred activations: unit (-1 = free)
   __shared__ uint32_t s_actd[ACT_SLOTS];  //   and the least distance pushed into it
   __shared__ int s_actn;                  //   units recorded
+  __shared__ int32_t s_xbk[XBUF ? XB_SLOTS : 1];             // buffered heads (-1 = free)
+  __shared__ unsigned long long s_xbv[XBUF ? XB_SLOTS : 1];  //   least candidate label
+  __shared__ int s_xbn;                                      //   heads buffered
+  __shared__ unsigned long long s_heap[HEAP ? HCAP : 1];     // heap mode: (dist, vertex) keys
+  __shared__ int s_hn, s_hu, s_hr0, s_hr1;                   //   size; popped vertex and row
+  __shared__ uint32_t s_hdu;                                 //   its distance
 
   const int tid0 = threadIdx.x;
+  if constexpr (XBUF) {
+    for (int i = tid0; i < XB_SLOTS; i += BS) {
+      s_xbk[i] = -1;
+      s_xbv[i] = ~0ull;
+    }
+    if (tid0 == 0) s_xbn = 0;
+  }
   for (int i = tid0; i < MAXB / 32; i += BS) s_mark[i] = 0u;
   for (int i = tid0; i < ACT_SLOTS; i += BS) {
     s_actk[i] = -1;
@@ -528,33 +665,37 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
     unsigned long long umin = s_red[0];
 #pragma unroll
     for (int k = 1; k < NW; k++) umin = s_red[k] < umin ? s_red[k] : umin;
-    const unsigned long long T = Dist<WT>::bucket_end(umin, delta);
-    // the lowest bucket is the frontier (with the distances just loaded);
-    // the rest goes back to the inbox, one atomic or per word
-    unsigned long long far = ~0ull;
-    for (int k = tid; k < nlist; k += BS) {
-      const uint32_t dv = s_d[k];
-      const int v = s_rs[k];
-      if ((unsigned long long)dv < T) {
-        const int slot = atomicAdd(&s_cnt, 1);
-        s_v[slot] = v;
-        s_vd[slot] = dv;
-      } else {
-        far = dv < far ? dv : far;
-        atomicOr(&s_fm[(v >> 5) - wlo], 1u << (v & 31));
+    unsigned long long T = 0;  // end of the bucket being settled (bucket modes)
+    int cnt = 0;               // its claimed vertices
+    if constexpr (!HEAP) {
+      T = Dist<WT>::bucket_end(umin, delta);
+      // the lowest bucket is the frontier (with the distances just loaded);
+      // the rest goes back to the inbox, one atomic or per word
+      unsigned long long far = ~0ull;
+      for (int k = tid; k < nlist; k += BS) {
+        const uint32_t dv = s_d[k];
+        const int v = s_rs[k];
+        if ((unsigned long long)dv < T) {
+          const int slot = atomicAdd(&s_cnt, 1);
+          s_v[slot] = v;
+          s_vd[slot] = dv;
+        } else {
+          far = dv < far ? dv : far;
+          atomicOr(&s_fm[(v >> 5) - wlo], 1u << (v & 31));
+        }
       }
+      far = wave_min(far);
+      if (lane == 0 && far != ~0ull) atomicMin(&s_far, far);
+      __syncthreads();
+      unsigned int putback = 0;
+      for (int i = tid; i <= whi - wlo; i += BS) {
+        const uint32_t fb = s_fm[i];
+        if (fb) putback += __popc(fb & ~aor(&dirty[wlo + i], fb));
+      }
+      putback = wave_sum(putback);
+      if (lane == 0 && putback) atomicAdd(&s_new, putback);
+      cnt = uni(s_cnt);
     }
-    far = wave_min(far);
-    if (lane == 0 && far != ~0ull) atomicMin(&s_far, far);
-    __syncthreads();
-    unsigned int putback = 0;
-    for (int i = tid; i <= whi - wlo; i += BS) {
-      const uint32_t fb = s_fm[i];
-      if (fb) putback += __popc(fb & ~aor(&dirty[wlo + i], fb));
-    }
-    putback = wave_sum(putback);
-    if (lane == 0 && putback) atomicAdd(&s_new, putback);
-    const int cnt = uni(s_cnt);
 
     // ---------------------------------------- 3-4. settle the bucket locally
     // Rounds: stage the frontier's rows, relax every arc; heads in this
@@ -564,248 +705,523 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
     // The batch first raises the pending count by RAISE, more than the inbox
     // bits all its rounds can set (at most m per round, MAX_ROUNDS_PER_BATCH
     // rounds), and returns the surplus once at the end.
-    int cur_cnt = cnt;
-    int nround = 0;
     long long raised = 0;  // thread 0 only
-    for (;;) {
+
+    // ------------------------------------------- 3-4. heap batch (SOLVE_HEAP)
+    // Alg. 3 taken literally inside the partition: every claimed inbox
+    // vertex goes into an LDS binary heap keyed by (distance, vertex); the
+    // batch pops the least entry, relaxes its arcs with the whole workgroup,
+    // pushes every head of this partition whose distance it lowered, and
+    // marks every lowered head of another partition in its owner's inbox
+    // (the message).  Lazy deletion: an entry whose vertex's label has
+    // dropped below its key since it was pushed is skipped (a lower entry,
+    // or an inbox bit, exists for that drop).  The batch drains the heap or
+    // stops after MAX_ROUNDS_PER_BATCH pops; entries left go back to the
+    // inbox.  Heap or list overflow sends a head to the inbox instead.
+    if constexpr (HEAP) {
       if (tid == 0) {
-        if (nround == 0) {
-          // the returned value is consumed so that the add has completed
-          // before thread 0 reaches the barrier below (no inbox bit of this
-          // batch is published before that barrier)
-          const long long before = aadd(&ctrl->work, RAISE);
-          raised = RAISE;
-          s_ncnt = before == LLONG_MIN ? 1 : 0;
-        } else {
-          s_ncnt = 0;
-        }
+        // raised before any inbox bit of this batch is published (the
+        // returned value is consumed so the add completes first)
+        const long long before = aadd(&ctrl->work, RAISE);
+        raised = RAISE;
+        int hn = 0;
+        for (int k = 0; k < nlist; k++)
+          s_heap[hn++] = ((unsigned long long)s_d[k] << 32) | (uint32_t)s_rs[k];
+        for (int i = hn / 2 - 1; i >= 0; i--) heap_down(s_heap, hn, i);
+        s_hn = before == LLONG_MIN ? 0 : hn;
       }
-      for (int k0 = 0; k0 < cur_cnt; k0 += BS * 4) {
-        unsigned long long lab[4];
-        int rs[4], re[4];
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-          const int k = k0 + j * BS + tid;
-          if (k < cur_cnt) {
-            const int u = s_v[k];
-            // round 0: the labels loaded after the claim; later rounds: the
-            // current label of each LDS-queued vertex
-            lab[j] = nround == 0 ? (unsigned long long)s_vd[k] << 32 : ld_rlx(&label[u]);
-            rs[j] = row_ptr[u];
-            re[j] = row_ptr[u + 1];
+      __syncthreads();
+      for (int pops = 0; pops < MAX_ROUNDS_PER_BATCH; pops++) {
+        if (tid == 0) {
+          int u = -1, r0 = 0, r1 = 0;
+          uint32_t du = 0;
+          int hn = s_hn;
+          while (hn > 0) {
+            const unsigned long long key = s_heap[0];
+            hn--;
+            if (hn > 0) {
+              s_heap[0] = s_heap[hn];
+              heap_down(s_heap, hn, 0);
+            }
+            const int v = (int)(uint32_t)key;
+            const uint32_t dk = (uint32_t)(key >> 32);
+            if ((uint32_t)(ld_rlx(&label[v]) >> 32) < dk) continue;  // stale entry
+            u = v;
+            du = dk;
+            break;
           }
-        }
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-          const int k = k0 + j * BS + tid;
-          if (k < cur_cnt) {
-            int r0 = rs[j], r1 = re[j];
+          s_hn = hn;
+          if (u >= 0) {
+            r0 = row_ptr[u];
+            r1 = row_ptr[u + 1];
             if (r0 < 0 || r1 < r0 || r1 > m) {
               set_status(&ctrl->status, SSSP_ERR_CSR);
               r0 = 0;
               r1 = 0;
             }
-            s_d[k] = (uint32_t)(lab[j] >> 32);
-            s_rs[k] = r0;
-            s_off[k] = r1 - r0;
           }
+          s_hu = u;
+          s_hdu = du;
+          s_hr0 = r0;
+          s_hr1 = r1;
+          s_ncnt = 0;
         }
-      }
-      __syncthreads();
-      int degs[EPT];
-      int lsum = 0;
+        __syncthreads();
+        const int u = uni(s_hu);
+        if (u < 0) break;
+        const uint32_t du = (uint32_t)uni((int)s_hdu);
+        const int r0 = uni(s_hr0);
+        const int deg = uni(s_hr1) - r0;
+        unsigned int upd = 0, cross = 0, nnew = 0;
+        unsigned long long pmin = ~0ull;
+        for (int b0 = 0; b0 < deg; b0 += BS * U) {
+          int e[U], v[U];
+          uint32_t wv[U], nd[U];
+          bool act[U];
 #pragma unroll
-      for (int j = 0; j < EPT; j++) {
-        const int k = tid * EPT + j;
-        degs[j] = k < cur_cnt ? s_off[k] : 0;
-        lsum += degs[j];
-      }
-      int tot;
-      int run = block_excl_scan1<BS>(lsum, s_ws, &tot);  // s_ws reused after later barriers
+          for (int j = 0; j < U; j++) {
+            const int idx = b0 + j * BS + tid;
+            act[j] = idx < deg;
+            if (act[j]) e[j] = r0 + idx;
+          }
 #pragma unroll
-      for (int j = 0; j < EPT; j++) {
-        const int k = tid * EPT + j;
-        if (k < cur_cnt) s_off[k] = run;
-        run += degs[j];
-      }
-      if (tid == 0) s_off[cur_cnt] = tot;
-      __syncthreads();
-
-      unsigned int upd = 0, cross = 0, nnew = 0;
-      unsigned long long pmin = ~0ull;
-      int hint = 0;
-      for (int b0 = 0; b0 < tot; b0 += BS * U) {
-        int e[U], v[U];
-        uint32_t du[U], wv[U], nd[U];
-        bool act[U];
-#pragma unroll
-        for (int j = 0; j < U; j++) {
-          const int idx = b0 + j * BS + tid;
-          act[j] = idx < tot;
-          if (act[j]) {
-            // last k with s_off[k] <= idx, galloping up from the previous k
-            int lo = hint, step = 1;
-            while (lo + step < cur_cnt && s_off[lo + step] <= idx) {
-              lo += step;
-              step <<= 1;
+          for (int j = 0; j < U; j++)
+            if (act[j]) {
+              v[j] = col[e[j]];
+              wv[j] = wgt[e[j]];
             }
-            int hi = min(lo + step, cur_cnt) - 1;
-            while (lo < hi) {
-              const int mid = (lo + hi + 1) >> 1;
-              if (s_off[mid] <= idx) lo = mid;
-              else hi = mid - 1;
+          unsigned long long pk[U], cur[U];
+#pragma unroll
+          for (int j = 0; j < U; j++) {
+            if (!act[j]) continue;
+            if ((unsigned)v[j] >= (unsigned)n) {
+              set_status(&ctrl->status, SSSP_ERR_CSR);
+              act[j] = false;
+              continue;
             }
-            hint = lo;
-            e[j] = s_rs[lo] + (idx - s_off[lo]);
-            du[j] = s_d[lo];
+            bool ovf;
+            nd[j] = Dist<WT>::add(du, wv[j], ovf);
+            if (ovf) {
+              st_rlx(&ctrl->ovf, 1u);  // decided after the solve, as in the bucket modes
+              act[j] = false;
+              continue;
+            }
+            if (v[j] == source) {
+              act[j] = false;
+              continue;
+            }
+            pk[j] = ((unsigned long long)nd[j] << 32) | (uint32_t)e[j];
+            cur[j] = ld_rlx(&label[v[j]]);
           }
-        }
 #pragma unroll
-        for (int j = 0; j < U; j++)
-          if (act[j]) {
-            v[j] = col[e[j]];
-            wv[j] = wgt[e[j]];
+          for (int j = 0; j < U; j++) {
+            if (act[j] && pk[j] < cur[j]) cur[j] = amin(&label[v[j]], pk[j]);
+            else act[j] = false;
           }
-        unsigned long long pk[U], cur[U];
+          bool inbox[U];
 #pragma unroll
-        for (int j = 0; j < U; j++) {
-          if (!act[j]) continue;
-          if ((unsigned)v[j] >= (unsigned)n) {
-            set_status(&ctrl->status, SSSP_ERR_CSR);
-            act[j] = false;
-            continue;
-          }
-          bool ovf;
-          nd[j] = Dist<WT>::add(du[j], wv[j], ovf);
-          if (ovf) {
-            // a candidate that does not fit is no shorter path to anything
-            // that fits: skip it.  Whether a final distance overflowed is
-            // decided after the fixed point (k_overflow_check); this flag
-            // only says that the check has to look.
-            st_rlx(&ctrl->ovf, 1u);
-            act[j] = false;
-            continue;
-          }
-          if (v[j] == source) {
-            act[j] = false;
-            continue;
-          }
-          pk[j] = ((unsigned long long)nd[j] << 32) | (uint32_t)e[j];
-          cur[j] = ld_rlx(&label[v[j]]);
-        }
-#pragma unroll
-        for (int j = 0; j < U; j++) {
-          if (act[j] && pk[j] < cur[j]) cur[j] = amin(&label[v[j]], pk[j]);
-          else act[j] = false;
-        }
-        // lowered distances: same partition and same bucket -> next round in
-        // LDS; otherwise -> the owner's inbox bit
-        bool inbox[U];
-#pragma unroll
-        for (int j = 0; j < U; j++) {
-          inbox[j] = false;
-          if (!act[j] || (uint32_t)(cur[j] >> 32) <= nd[j]) {
-            act[j] = false;
-            continue;
-          }
-          upd++;
-          const int q = v[j] / bsize;
-          if (q != part) {
-            cross++;
-            inbox[j] = true;
-          } else if ((unsigned long long)nd[j] < T) {
-            const int lv = v[j] - vlo;
-            const uint32_t mb = 1u << (lv & 31);
-            if (!(atomicOr(&s_mark[lv >> 5], mb) & mb)) {
+          for (int j = 0; j < U; j++) {
+            inbox[j] = false;
+            if (!act[j] || (uint32_t)(cur[j] >> 32) <= nd[j]) {
+              act[j] = false;
+              continue;
+            }
+            upd++;
+            if (v[j] / bsize != part) {
+              cross++;
+              inbox[j] = true;
+            } else {
+              // pq.push(v): one entry per lowering, pushed after the row
               const int slot = atomicAdd(&s_ncnt, 1);
-              if (slot < FCAP) s_nv[slot] = v[j];
-              else {
-                atomicAnd(&s_mark[lv >> 5], ~mb);
+              if (slot < FCAP) {
+                s_nv[slot] = v[j];
+                s_vd[slot] = nd[j];
+              } else {
                 inbox[j] = true;
               }
             }
-          } else {
-            inbox[j] = true;
           }
-        }
-        uint32_t ob[U];
+          uint32_t ob[U];
 #pragma unroll
-        for (int j = 0; j < U; j++)
-          if (inbox[j]) ob[j] = aor(&dirty[v[j] >> 5], 1u << (v[j] & 31));
+          for (int j = 0; j < U; j++)
+            if (inbox[j]) ob[j] = aor(&dirty[v[j] >> 5], 1u << (v[j] & 31));
 #pragma unroll
-        for (int j = 0; j < U; j++) {
-          if (!inbox[j] || ((ob[j] >> (v[j] & 31)) & 1u)) continue;  // already pending
-          nnew++;
-          const int q = v[j] / bsize;
-          if (q != part) {
-            const int gu = unit0 + q;
-            if (!act_defer(s_actk, s_actd, &s_actn, gu, nd[j])) {
-              amin(&unit_min[gu], (unsigned long long)nd[j]);
-              aor(&abits[abw(gu)], abit(gu));
+          for (int j = 0; j < U; j++) {
+            if (!inbox[j] || ((ob[j] >> (v[j] & 31)) & 1u)) continue;  // already pending
+            nnew++;
+            const int q = v[j] / bsize;
+            if (q != part) {
+              const int gu = unit0 + q;
+              if (!act_defer(s_actk, s_actd, &s_actn, gu, nd[j])) {
+                amin(&unit_min[gu], (unsigned long long)nd[j]);
+                aor(&abits[abw(gu)], abit(gu));
+              }
+            } else {
+              pmin = nd[j] < pmin ? nd[j] : pmin;
             }
-          } else {
-            pmin = nd[j] < pmin ? nd[j] : pmin;
           }
         }
+        upd = wave_sum(upd);
+        cross = wave_sum(cross);
+        nnew = wave_sum(nnew);
+        pmin = wave_min(pmin);
+        if (lane == 0) {
+          if (upd) atomicAdd(&s_upd, upd);
+          if (cross) atomicAdd(&s_cross, cross);
+          if (nnew) atomicAdd(&s_new, nnew);
+          if (pmin != ~0ull) atomicMin(&s_lmin, pmin);
+        }
+        if (tid == 0) {
+          s_tot += deg;
+          s_exp += 1;
+        }
+        __syncthreads();
+        if (tid == 0) {
+          // push the lowered local heads; a full heap sends them to the inbox
+          const int k = min(s_ncnt, FCAP);
+          int hn = s_hn;
+          unsigned int spill = 0;
+          unsigned long long smin = ~0ull;
+          for (int i = 0; i < k; i++) {
+            const unsigned long long key =
+                ((unsigned long long)s_vd[i] << 32) | (uint32_t)s_nv[i];
+            if (hn < HCAP) {
+              heap_up(s_heap, hn, key);
+              hn++;
+            } else {
+              const int v2 = s_nv[i];
+              const uint32_t bit = 1u << (v2 & 31);
+              if (!(aor(&dirty[v2 >> 5], bit) & bit)) spill++;
+              smin = s_vd[i] < smin ? s_vd[i] : smin;
+            }
+          }
+          s_hn = hn;
+          if (spill) s_new += spill;
+          if (smin != ~0ull) s_lmin = smin < s_lmin ? smin : s_lmin;
+        }
+        if (s_actn <= ACT_FEW) {  // few units pushed into: wake them now
+          for (int i = tid; i < ACT_SLOTS; i += BS) {
+            const int gu = s_actk[i];
+            if (gu >= 0) {
+              amin(&unit_min[gu], (unsigned long long)s_actd[i]);
+              aor(&abits[abw(gu)], abit(gu));
+              s_actk[i] = -1;
+              s_actd[i] = 0xFFFFFFFFu;
+            }
+          }
+          __syncthreads();
+          if (tid == 0) s_actn = 0;
+        }
+        __syncthreads();
       }
-      upd = wave_sum(upd);
-      cross = wave_sum(cross);
-      nnew = wave_sum(nnew);
-      pmin = wave_min(pmin);
+      // entries left in the heap go back to the inbox (stale ones need not)
+      unsigned int back = 0;
+      unsigned long long bmin = ~0ull;
+      const int hleft = uni(s_hn);
+      for (int i = tid; i < hleft; i += BS) {
+        const unsigned long long key = s_heap[i];
+        const int v2 = (int)(uint32_t)key;
+        const uint32_t dk = (uint32_t)(key >> 32);
+        if ((uint32_t)(ld_rlx(&label[v2]) >> 32) < dk) continue;
+        const uint32_t bit = 1u << (v2 & 31);
+        if (!(aor(&dirty[v2 >> 5], bit) & bit)) back++;
+        bmin = dk < bmin ? dk : bmin;
+      }
+      back = wave_sum(back);
+      bmin = wave_min(bmin);
       if (lane == 0) {
-        if (upd) atomicAdd(&s_upd, upd);
-        if (cross) atomicAdd(&s_cross, cross);
-        if (nnew) atomicAdd(&s_new, nnew);
-        if (pmin != ~0ull) atomicMin(&s_lmin, pmin);
-      }
-      if (tid == 0) {
-        s_tot += tot;
-        s_exp += cur_cnt;
+        if (back) atomicAdd(&s_new, back);
+        if (bmin != ~0ull) atomicMin(&s_lmin, bmin);
       }
       __syncthreads();
-      if (s_actn <= ACT_FEW) {  // few units pushed into: wake them now
-        for (int i = tid; i < ACT_SLOTS; i += BS) {
-          const int gu = s_actk[i];
-          if (gu >= 0) {
-            amin(&unit_min[gu], (unsigned long long)s_actd[i]);
-            aor(&abits[abw(gu)], abit(gu));
-            s_actk[i] = -1;
-            s_actd[i] = 0xFFFFFFFFu;
+    } else {
+      int cur_cnt = cnt;
+      int nround = 0;
+      for (;;) {
+        if (tid == 0) {
+          if (nround == 0) {
+            // the returned value is consumed so that the add has completed
+            // before thread 0 reaches the barrier below (no inbox bit of this
+            // batch is published before that barrier)
+            const long long before = aadd(&ctrl->work, RAISE);
+            raised = RAISE;
+            s_ncnt = before == LLONG_MIN ? 1 : 0;
+          } else {
+            s_ncnt = 0;
+          }
+        }
+        for (int k0 = 0; k0 < cur_cnt; k0 += BS * 4) {
+          unsigned long long lab[4];
+          int rs[4], re[4];
+  #pragma unroll
+          for (int j = 0; j < 4; j++) {
+            const int k = k0 + j * BS + tid;
+            if (k < cur_cnt) {
+              const int u = s_v[k];
+              // round 0: the labels loaded after the claim; later rounds: the
+              // current label of each LDS-queued vertex
+              lab[j] = nround == 0 ? (unsigned long long)s_vd[k] << 32 : ld_rlx(&label[u]);
+              rs[j] = row_ptr[u];
+              re[j] = row_ptr[u + 1];
+            }
+          }
+  #pragma unroll
+          for (int j = 0; j < 4; j++) {
+            const int k = k0 + j * BS + tid;
+            if (k < cur_cnt) {
+              int r0 = rs[j], r1 = re[j];
+              if (r0 < 0 || r1 < r0 || r1 > m) {
+                set_status(&ctrl->status, SSSP_ERR_CSR);
+                r0 = 0;
+                r1 = 0;
+              }
+              s_d[k] = (uint32_t)(lab[j] >> 32);
+              s_rs[k] = r0;
+              s_off[k] = r1 - r0;
+            }
           }
         }
         __syncthreads();
-        if (tid == 0) s_actn = 0;
-      }
-      const int ncnt = uni(min(s_ncnt, FCAP));
-      nround++;
-      if (ncnt == 0) break;
-      if (nround >= MAX_ROUNDS_PER_BATCH) {
-        // hand the queued vertices back to the inbox (covered by this
-        // round's raise) and stop
-        unsigned int fl = 0;
+        int degs[EPT];
+        int lsum = 0;
+  #pragma unroll
+        for (int j = 0; j < EPT; j++) {
+          const int k = tid * EPT + j;
+          degs[j] = k < cur_cnt ? s_off[k] : 0;
+          lsum += degs[j];
+        }
+        int tot;
+        int run = block_excl_scan1<BS>(lsum, s_ws, &tot);  // s_ws reused after later barriers
+  #pragma unroll
+        for (int j = 0; j < EPT; j++) {
+          const int k = tid * EPT + j;
+          if (k < cur_cnt) s_off[k] = run;
+          run += degs[j];
+        }
+        if (tid == 0) s_off[cur_cnt] = tot;
+        __syncthreads();
+
+        unsigned int upd = 0, cross = 0, nnew = 0;
+        unsigned long long pmin = ~0ull;
+        int hint = 0;
+        for (int b0 = 0; b0 < tot; b0 += BS * U) {
+          int e[U], v[U];
+          uint32_t du[U], wv[U], nd[U];
+          bool act[U];
+  #pragma unroll
+          for (int j = 0; j < U; j++) {
+            const int idx = b0 + j * BS + tid;
+            act[j] = idx < tot;
+            if (act[j]) {
+              // last k with s_off[k] <= idx, galloping up from the previous k
+              int lo = hint, step = 1;
+              while (lo + step < cur_cnt && s_off[lo + step] <= idx) {
+                lo += step;
+                step <<= 1;
+              }
+              int hi = min(lo + step, cur_cnt) - 1;
+              while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= idx) lo = mid;
+                else hi = mid - 1;
+              }
+              hint = lo;
+              e[j] = s_rs[lo] + (idx - s_off[lo]);
+              du[j] = s_d[lo];
+            }
+          }
+  #pragma unroll
+          for (int j = 0; j < U; j++)
+            if (act[j]) {
+              v[j] = col[e[j]];
+              wv[j] = wgt[e[j]];
+            }
+          unsigned long long pk[U], cur[U];
+  #pragma unroll
+          for (int j = 0; j < U; j++) {
+            if (!act[j]) continue;
+            if ((unsigned)v[j] >= (unsigned)n) {
+              set_status(&ctrl->status, SSSP_ERR_CSR);
+              act[j] = false;
+              continue;
+            }
+            bool ovf;
+            nd[j] = Dist<WT>::add(du[j], wv[j], ovf);
+            if (ovf) {
+              // a candidate that does not fit is no shorter path to anything
+              // that fits: skip it.  Whether a final distance overflowed is
+              // decided after the fixed point (k_overflow_check); this flag
+              // only says that the check has to look.
+              st_rlx(&ctrl->ovf, 1u);
+              act[j] = false;
+              continue;
+            }
+            if (v[j] == source) {
+              act[j] = false;
+              continue;
+            }
+            pk[j] = ((unsigned long long)nd[j] << 32) | (uint32_t)e[j];
+            cur[j] = ld_rlx(&label[v[j]]);
+          }
+          if constexpr (XBUF) {
+            // cross-partition candidates that beat the current label wait in
+            // the LDS buffer (applied once per distinct head at the flush)
+  #pragma unroll
+            for (int j = 0; j < U; j++)
+              if (act[j] && pk[j] < cur[j] && v[j] / bsize != part &&
+                  xb_insert(s_xbk, s_xbv, &s_xbn, v[j], pk[j]))
+                act[j] = false;
+          }
+  #pragma unroll
+          for (int j = 0; j < U; j++) {
+            if (act[j] && pk[j] < cur[j]) cur[j] = amin(&label[v[j]], pk[j]);
+            else act[j] = false;
+          }
+          // lowered distances: same partition and same bucket -> next round in
+          // LDS; otherwise -> the owner's inbox bit
+          bool inbox[U];
+  #pragma unroll
+          for (int j = 0; j < U; j++) {
+            inbox[j] = false;
+            if (!act[j] || (uint32_t)(cur[j] >> 32) <= nd[j]) {
+              act[j] = false;
+              continue;
+            }
+            upd++;
+            const int q = v[j] / bsize;
+            if (q != part) {
+              cross++;
+              inbox[j] = true;
+            } else if ((unsigned long long)nd[j] < T) {
+              const int lv = v[j] - vlo;
+              const uint32_t mb = 1u << (lv & 31);
+              if (!(atomicOr(&s_mark[lv >> 5], mb) & mb)) {
+                const int slot = atomicAdd(&s_ncnt, 1);
+                if (slot < FCAP) s_nv[slot] = v[j];
+                else {
+                  atomicAnd(&s_mark[lv >> 5], ~mb);
+                  inbox[j] = true;
+                }
+              }
+            } else {
+              inbox[j] = true;
+            }
+          }
+          uint32_t ob[U];
+  #pragma unroll
+          for (int j = 0; j < U; j++)
+            if (inbox[j]) ob[j] = aor(&dirty[v[j] >> 5], 1u << (v[j] & 31));
+  #pragma unroll
+          for (int j = 0; j < U; j++) {
+            if (!inbox[j] || ((ob[j] >> (v[j] & 31)) & 1u)) continue;  // already pending
+            nnew++;
+            const int q = v[j] / bsize;
+            if (q != part) {
+              const int gu = unit0 + q;
+              if (!act_defer(s_actk, s_actd, &s_actn, gu, nd[j])) {
+                amin(&unit_min[gu], (unsigned long long)nd[j]);
+                aor(&abits[abw(gu)], abit(gu));
+              }
+            } else {
+              pmin = nd[j] < pmin ? nd[j] : pmin;
+            }
+          }
+        }
+        upd = wave_sum(upd);
+        cross = wave_sum(cross);
+        nnew = wave_sum(nnew);
+        pmin = wave_min(pmin);
+        if (lane == 0) {
+          if (upd) atomicAdd(&s_upd, upd);
+          if (cross) atomicAdd(&s_cross, cross);
+          if (nnew) atomicAdd(&s_new, nnew);
+          if (pmin != ~0ull) atomicMin(&s_lmin, pmin);
+        }
+        if (tid == 0) {
+          s_tot += tot;
+          s_exp += cur_cnt;
+        }
+        __syncthreads();
+        if constexpr (XBUF) {
+          if (s_xbn >= SSSP_XB_FLUSH) {  // push out on count
+            unsigned int fu = 0, fc = 0, fn = 0;
+            xb_flush<BS>(s_xbk, s_xbv, label, dirty, bsize, unit0, unit_min, abits, s_actk, s_actd,
+                         &s_actn, fu, fc, fn);
+            fu = wave_sum(fu);
+            fc = wave_sum(fc);
+            fn = wave_sum(fn);
+            if (lane == 0) {
+              if (fu) atomicAdd(&s_upd, fu);
+              if (fc) atomicAdd(&s_cross, fc);
+              if (fn) atomicAdd(&s_new, fn);
+            }
+            __syncthreads();
+            if (tid == 0) s_xbn = 0;
+          }
+        }
+        if (s_actn <= ACT_FEW) {  // few units pushed into: wake them now
+          for (int i = tid; i < ACT_SLOTS; i += BS) {
+            const int gu = s_actk[i];
+            if (gu >= 0) {
+              amin(&unit_min[gu], (unsigned long long)s_actd[i]);
+              aor(&abits[abw(gu)], abit(gu));
+              s_actk[i] = -1;
+              s_actd[i] = 0xFFFFFFFFu;
+            }
+          }
+          __syncthreads();
+          if (tid == 0) s_actn = 0;
+        }
+        const int ncnt = uni(min(s_ncnt, FCAP));
+        nround++;
+        if (ncnt == 0) break;
+        if (nround >= MAX_ROUNDS_PER_BATCH) {
+          // hand the queued vertices back to the inbox (covered by this
+          // round's raise) and stop
+          unsigned int fl = 0;
+          for (int k = tid; k < ncnt; k += BS) {
+            const int v2 = s_nv[k];
+            const int lv = v2 - vlo;
+            atomicAnd(&s_mark[lv >> 5], ~(1u << (lv & 31)));
+            const uint32_t bit = 1u << (v2 & 31);
+            if (!(aor(&dirty[v2 >> 5], bit) & bit)) fl++;
+          }
+          fl = wave_sum(fl);
+          if (lane == 0 && fl) atomicAdd(&s_new, fl);
+          if (tid == 0) atomicMin(&s_lmin, umin);
+          __syncthreads();
+          break;
+        }
         for (int k = tid; k < ncnt; k += BS) {
           const int v2 = s_nv[k];
           const int lv = v2 - vlo;
           atomicAnd(&s_mark[lv >> 5], ~(1u << (lv & 31)));
-          const uint32_t bit = 1u << (v2 & 31);
-          if (!(aor(&dirty[v2 >> 5], bit) & bit)) fl++;
+          s_v[k] = v2;
         }
-        fl = wave_sum(fl);
-        if (lane == 0 && fl) atomicAdd(&s_new, fl);
-        if (tid == 0) atomicMin(&s_lmin, umin);
+        cur_cnt = ncnt;
         __syncthreads();
-        break;
       }
-      for (int k = tid; k < ncnt; k += BS) {
-        const int v2 = s_nv[k];
-        const int lv = v2 - vlo;
-        atomicAnd(&s_mark[lv >> 5], ~(1u << (lv & 31)));
-        s_v[k] = v2;
-      }
-      cur_cnt = ncnt;
-      __syncthreads();
     }
 
+    if constexpr (XBUF) {
+      // push out what the batch still buffers (it records wakeups, which
+      // are published next)
+      if (s_xbn > 0) {
+        unsigned int fu = 0, fc = 0, fn = 0;
+        xb_flush<BS>(s_xbk, s_xbv, label, dirty, bsize, unit0, unit_min, abits, s_actk, s_actd,
+                     &s_actn, fu, fc, fn);
+        fu = wave_sum(fu);
+        fc = wave_sum(fc);
+        fn = wave_sum(fn);
+        if (lane == 0) {
+          if (fu) atomicAdd(&s_upd, fu);
+          if (fc) atomicAdd(&s_cross, fc);
+          if (fn) atomicAdd(&s_new, fn);
+        }
+        __syncthreads();
+        if (tid == 0) s_xbn = 0;
+      }
+    }
     // deferred activations of the units this batch pushed into: published
     // before the settle below returns the batch's surplus of pending work
     for (int i = tid; i < ACT_SLOTS; i += BS) {
@@ -1004,38 +1420,43 @@ hipError_t launch_init(const SolveArgs &a, int nsolves, int max_n, hipStream_t s
   return hipGetLastError();
 }
 
-template <int WT, int BS>
-static hipError_t launch_solve_t(const SolveArgs &a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_solve<WT, BS>), dim3(grid), dim3(BS), 0, st, a);
+// The kernel instance for (weight type, block size, mode): launched, or
+// asked for its residency.
+template <int WT, int BS, int MODE>
+static hipError_t solve_kernel_op(const SolveArgs *a, int grid, hipStream_t st, int *per_cu) {
+  if (per_cu) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_solve<WT, BS, MODE>,
+                                                                  BS, 0);
+  hipLaunchKernelGGL((k_solve<WT, BS, MODE>), dim3(grid), dim3(BS), 0, st, *a);
   return hipGetLastError();
 }
 
-hipError_t launch_solve(const SolveArgs &a, int wtype, int bs, int grid, hipStream_t st) {
-  if (wtype == SSSP_W_U32) {
-    if (bs == 256) return launch_solve_t<SSSP_W_U32, 256>(a, grid, st);
-    if (bs == 512) return launch_solve_t<SSSP_W_U32, 512>(a, grid, st);
-    return launch_solve_t<SSSP_W_U32, 1024>(a, grid, st);
-  }
-  if (bs == 256) return launch_solve_t<SSSP_W_F32, 256>(a, grid, st);
-  if (bs == 512) return launch_solve_t<SSSP_W_F32, 512>(a, grid, st);
-  return launch_solve_t<SSSP_W_F32, 1024>(a, grid, st);
+template <int WT, int BS>
+static hipError_t solve_kernel_mode(int mode, const SolveArgs *a, int grid, hipStream_t st,
+                                    int *per_cu) {
+  if (mode == SOLVE_BUFFERED) return solve_kernel_op<WT, BS, SOLVE_BUFFERED>(a, grid, st, per_cu);
+  if (mode == SOLVE_HEAP) return solve_kernel_op<WT, BS, SOLVE_HEAP>(a, grid, st, per_cu);
+  return solve_kernel_op<WT, BS, SOLVE_BUCKETS>(a, grid, st, per_cu);
 }
 
-int solve_max_blocks_per_cu(int wtype, int bs) {
+template <int WT>
+static hipError_t solve_kernel_bs(int bs, int mode, const SolveArgs *a, int grid, hipStream_t st,
+                                  int *per_cu) {
+  if (bs == 256) return solve_kernel_mode<WT, 256>(mode, a, grid, st, per_cu);
+  if (bs == 512) return solve_kernel_mode<WT, 512>(mode, a, grid, st, per_cu);
+  return solve_kernel_mode<WT, 1024>(mode, a, grid, st, per_cu);
+}
+
+hipError_t launch_solve(const SolveArgs &a, int wtype, int bs, int mode, int grid,
+                        hipStream_t st) {
+  if (wtype == SSSP_W_U32) return solve_kernel_bs<SSSP_W_U32>(bs, mode, &a, grid, st, nullptr);
+  return solve_kernel_bs<SSSP_W_F32>(bs, mode, &a, grid, st, nullptr);
+}
+
+int solve_max_blocks_per_cu(int wtype, int bs, int mode) {
   int nb = 0;
-  hipError_t e;
-#define SSSP_OCC(WT, BS)                                                                   \
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_solve<WT, BS>, BS, 0);
-  if (wtype == SSSP_W_U32) {
-    if (bs == 256) { SSSP_OCC(SSSP_W_U32, 256) }
-    else if (bs == 512) { SSSP_OCC(SSSP_W_U32, 512) }
-    else { SSSP_OCC(SSSP_W_U32, 1024) }
-  } else {
-    if (bs == 256) { SSSP_OCC(SSSP_W_F32, 256) }
-    else if (bs == 512) { SSSP_OCC(SSSP_W_F32, 512) }
-    else { SSSP_OCC(SSSP_W_F32, 1024) }
-  }
-#undef SSSP_OCC
+  const hipError_t e =
+      wtype == SSSP_W_U32 ? solve_kernel_bs<SSSP_W_U32>(bs, mode, nullptr, 0, nullptr, &nb)
+                          : solve_kernel_bs<SSSP_W_F32>(bs, mode, nullptr, 0, nullptr, &nb);
   return e == hipSuccess && nb > 0 ? nb : 1;
 }
 

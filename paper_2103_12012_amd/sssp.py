@@ -23,6 +23,7 @@ HEADER = os.path.join(_HERE, "..", "include", "sssp.h")
 
 W_U32, W_F32 = 0, 1
 F_VALIDATE, F_SYNC, F_PRUNE_LOCAL, F_NO_AUTOTUNE = 1, 2, 4, 8
+F_BUFFER_CROSS, F_LOCAL_HEAP = 16, 32
 
 ERRORS = {
     0: "SSSP_OK", -1: "SSSP_ERR_ARG", -2: "SSSP_ERR_SOURCE", -3: "SSSP_ERR_CSR",
@@ -152,9 +153,10 @@ def _csr(row_ptr, col, w) -> CSR:
 
 def make_opts(delta=0.0, num_partitions=0, wg_size=0, num_workgroups=0, max_rounds=0,
               validate=True, sync=False, local=False, no_autotune=False, events=None,
-              lag=0) -> Opts:
+              lag=0, buffer_cross=False, local_heap=False) -> Opts:
     flags = (F_VALIDATE if validate else 0) | (F_SYNC if sync else 0) | \
-            (F_PRUNE_LOCAL if local else 0) | (F_NO_AUTOTUNE if no_autotune else 0)
+            (F_PRUNE_LOCAL if local else 0) | (F_NO_AUTOTUNE if no_autotune else 0) | \
+            (F_BUFFER_CROSS if buffer_cross else 0) | (F_LOCAL_HEAP if local_heap else 0)
     o = Opts()
     o.delta = float(delta)
     o.num_partitions = int(num_partitions)
@@ -235,11 +237,13 @@ class Solver:
 
     def __init__(self, row_ptr, col, w, *, delta=0.0, num_partitions=0, wg_size=0,
                  num_workgroups=0, max_rounds=0, validate=True, want_pred=True,
-                 stats=False, lag=0, no_autotune=False):
+                 stats=False, lag=0, no_autotune=False, buffer_cross=False,
+                 local_heap=False):
         self.g = _csr(row_ptr, col, w)
         self._keep = (row_ptr, col, w)
         self.opts = make_opts(delta, num_partitions, wg_size, num_workgroups, max_rounds,
-                              validate=validate, lag=lag, no_autotune=no_autotune)
+                              validate=validate, lag=lag, no_autotune=no_autotune,
+                              buffer_cross=buffer_cross, local_heap=local_heap)
         dev = col.device
         self.col_device = dev
         n = self.g.n
@@ -289,7 +293,8 @@ class BatchSolver:
     outputs are allocated once so the call can be captured and replayed."""
 
     def __init__(self, graphs, solve_graph, solve_source, *, delta=0.0, num_partitions=0,
-                 wg_size=0, num_workgroups=0, validate=False, want_pred=True, stats=False):
+                 wg_size=0, num_workgroups=0, validate=False, want_pred=True, stats=False,
+                 buffer_cross=False, local_heap=False):
         self._keep = graphs
         self.gs = (CSR * len(graphs))(*[_csr(*g) for g in graphs])
         wdt = graphs[0][2].dtype
@@ -304,7 +309,8 @@ class BatchSolver:
         self.out_offset = (ctypes.c_int64 * len(offs))(*offs)
         self.total = tot
         self.opts = make_opts(delta, num_partitions, wg_size, num_workgroups,
-                              validate=validate)
+                              validate=validate, buffer_cross=buffer_cross,
+                              local_heap=local_heap)
         self.dist = torch.empty(tot, dtype=wdt, device=dev)
         self.pred = torch.empty(tot, dtype=torch.int32, device=dev) if want_pred else None
         self.pred_edge = torch.empty(tot, dtype=torch.int32, device=dev)

@@ -97,11 +97,13 @@ def test_batch_autotune_then_parity(tmp_path):
     check(graphs, sg, ss, (b.split(b.dist), b.split(b.pred), b.split(b.pred_edge)))
 
 
-def test_c4_full_size_batched_launch():
+@pytest.mark.parametrize("buffer_cross", [False, True])
+def test_c4_full_size_batched_launch(buffer_cross):
     """The batched workload at full size, as the benchmark runs it: 64 R-MAT
     graphs of scales 12..18 (seed 4, graph i seed 4000+i), 4 random sources
     each, tuned as a whole and launched once through a captured HIP graph;
-    every one of the 256 results equals the single-source oracle."""
+    every one of the 256 results equals the single-source oracle (also with
+    buffered cross-partition updates)."""
     rng = np.random.default_rng(4)
     scales = rng.integers(12, 19, size=64)
     graphs = [gen.rmat(int(sc), 4000 + i) for i, sc in enumerate(scales)]
@@ -112,7 +114,7 @@ def test_c4_full_size_batched_launch():
             ss.append(int(s))
     S = sssp_mod()
     dg = [dev(g) for g in graphs]
-    b = S.BatchSolver(dg, sg, ss)
+    b = S.BatchSolver(dg, sg, ss, buffer_cross=buffer_cross)
     b.autotune()
     b()
     torch.cuda.synchronize()
