@@ -110,7 +110,21 @@ enum {
      the inbox).  delta plays no part in a batch (the lag window still
      bounds which partitions may run).  Results are the same.  Not together
      with SSSP_F_BUFFER_CROSS (SSSP_ERR_ARG). */
-  SSSP_F_LOCAL_HEAP = 1u << 5
+  SSSP_F_LOCAL_HEAP = 1u << 5,
+  /* sssp_solve only: idle-time pruning (Sec. III-B: processes that receive
+     no message prune their subgraph meanwhile, and the solve skips what
+     they delete; Sec. II: pruning overlapped with the SSSP computation).
+     A workgroup that finds no partition to settle runs Trishla with LOCAL
+     scope (the middle vertex in the tail's own partition) over a chunk of
+     64 vertices and marks the arcs it deletes; the solve no longer relaxes
+     them.  Which arcs are deleted depends on timing (a row of more than
+     1024 arcs or more than 65536 two-arc paths is skipped, and the solve
+     ends when no work is pending, pruned or not), but every deleted arc is
+     in the LOCAL deletion set, so distances and predecessors are the same.
+     opts->keep_out, if set, receives the keep flags; stats->edges_pruned and
+     stats->wedges count deleted arcs and two-arc paths examined.  Not
+     together with the two modes above (SSSP_ERR_ARG). */
+  SSSP_F_IDLE_PRUNE = 1u << 6
 };
 
 typedef struct {
@@ -144,6 +158,9 @@ typedef struct {
   void *event_start;       /* optional hipEvent_t recorded right before the
                               main kernel of the call (NULL = none)        */
   void *event_stop;        /* optional hipEvent_t recorded right after it  */
+  void *keep_out;          /* SSSP_F_IDLE_PRUNE: optional device uint8[m]
+                              receiving 1 for every arc kept and 0 for every
+                              arc deleted during the solve (NULL = none)   */
 } sssp_opts;
 
 /* Fill *o with the defaults (everything automatic). */

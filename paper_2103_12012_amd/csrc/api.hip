@@ -71,7 +71,9 @@ int check_opts(const sssp_opts *o) {
     return SSSP_ERR_ARG;
   if (o->num_partitions < 0 || o->num_workgroups < 0 || o->max_rounds < 0) return SSSP_ERR_ARG;
   if (std::isnan(o->delta)) return SSSP_ERR_ARG;
-  if ((o->flags & SSSP_F_LOCAL_HEAP) && (o->flags & SSSP_F_BUFFER_CROSS)) return SSSP_ERR_ARG;
+  const int modes = ((o->flags & SSSP_F_LOCAL_HEAP) != 0) + ((o->flags & SSSP_F_BUFFER_CROSS) != 0) +
+                    ((o->flags & SSSP_F_IDLE_PRUNE) != 0);
+  if (modes > 1) return SSSP_ERR_ARG;
   return SSSP_OK;
 }
 
@@ -178,6 +180,7 @@ int plan_grid(int wtype, int bs, int want, int per_cu_default, int mode) {
 
 // Solve mode (k_solve's local rule and update path) chosen by the flags.
 int solve_mode(uint32_t flags) {
+  if (flags & SSSP_F_IDLE_PRUNE) return SOLVE_IDLE_PRUNE;
   if (flags & SSSP_F_LOCAL_HEAP) return SOLVE_HEAP;
   if (flags & SSSP_F_BUFFER_CROSS) return SOLVE_BUFFERED;
   return SOLVE_BUCKETS;
@@ -185,11 +188,12 @@ int solve_mode(uint32_t flags) {
 
 // Workspace layout of a (batched) solve.
 struct SolveLayout {
-  size_t desc = 0, unit_solve = 0, unit_min = 0, abits = 0, ctrl = 0, total = 0;
+  size_t desc = 0, unit_solve = 0, unit_min = 0, abits = 0, ctrl = 0, keep = 0, total = 0;
   std::vector<size_t> label, dirty;
 };
 
-SolveLayout solve_layout(int nsolves, const std::vector<int> &ns, int nunits) {
+// keep_arcs > 0: one keep bit per arc for idle-time pruning (single solve).
+SolveLayout solve_layout(int nsolves, const std::vector<int> &ns, int nunits, int keep_arcs = 0) {
   SolveLayout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -209,6 +213,7 @@ SolveLayout solve_layout(int nsolves, const std::vector<int> &ns, int nunits) {
     L.label[i] = take(sizeof(unsigned long long) * (size_t)ns[i]);
     L.dirty[i] = take(sizeof(uint32_t) * (size_t)((ns[i] + 31) / 32));
   }
+  if (keep_arcs > 0) L.keep = take(sizeof(uint32_t) * (size_t)((keep_arcs + 31) / 32));
   L.total = off;
   return L;
 }
@@ -252,6 +257,12 @@ int run_solves(std::vector<SolveDesc> &descs, const SolveLayout &L, int nunits, 
   a.num_solves = (int)descs.size();
   a.window = DELTA_INF;
   a.auto_lag = 0;
+  if (solve_mode(o.flags) == SOLVE_IDLE_PRUNE && descs.size() == 1 && descs[0].m > 0) {
+    a.keepbits = reinterpret_cast<uint32_t *>(ws + L.keep);
+    a.keep_out = static_cast<uint8_t *>(o.keep_out);
+    a.desc_m0 = descs[0].m;
+    a.prune_tasks = (descs[0].n + PRUNE_CHUNK - 1) / PRUNE_CHUNK;
+  }
   if (descs.size() == 1 && o.lag >= 0 && descs[0].delta != DELTA_INF) {
     const unsigned long long lag = o.lag > 0 ? (unsigned long long)o.lag : 1ull;
     if (descs[0].delta == DELTA_AUTO) a.auto_lag = (int)lag;
@@ -287,6 +298,7 @@ int run_solves(std::vector<SolveDesc> &descs, const SolveLayout &L, int nunits, 
   if (o.event_stop && hipEventRecord((hipEvent_t)o.event_stop, st) != hipSuccess)
     return SSSP_ERR_HIP;
   if (launch_epilogue(a, wtype, ns, max_n, st) != hipSuccess) return SSSP_ERR_HIP;
+  if (a.keep_out && launch_keep_out(a, st) != hipSuccess) return SSSP_ERR_HIP;
   if (o.flags & SSSP_F_SYNC) return finish_sync(&a.ctrl->status, st);
   return SSSP_OK;
 }
@@ -314,7 +326,8 @@ extern "C" int sssp_solve(const sssp_csr *g, int32_t source, const sssp_opts *o,
   if ((rc = check_opts(&opts))) return rc;
   if (source < 0 || source >= g->n) return SSSP_ERR_SOURCE;
   const SolvePlan pl = make_plan(*g, opts);
-  const SolveLayout L = solve_layout(1, std::vector<int>{g->n}, pl.nparts);
+  const bool iprune = solve_mode(opts.flags) == SOLVE_IDLE_PRUNE;
+  const SolveLayout L = solve_layout(1, std::vector<int>{g->n}, pl.nparts, iprune ? g->m : 0);
   if (!ws) {
     *ws_bytes = L.total;
     return SSSP_OK;
@@ -358,6 +371,7 @@ extern "C" int sssp_solve_batch(int32_t num_graphs, const sssp_csr *graphs, int3
   if (num_graphs < 1 || num_solves < 1 || num_solves > 65535 || !graphs || !solve_graph ||
       !solve_source || !out_offset || !ws_bytes)
     return SSSP_ERR_ARG;
+  if (o && (o->flags & SSSP_F_IDLE_PRUNE)) return SSSP_ERR_ARG;  // single solves only
   int rc;
   for (int i = 0; i < num_graphs; i++) {
     if ((rc = check_csr(&graphs[i]))) return rc;

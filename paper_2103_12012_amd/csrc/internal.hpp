@@ -21,8 +21,10 @@ constexpr int ABW_UNITS = 8;                     // units per active-unit bitmap
 enum SolveMode {
   SOLVE_BUCKETS = 0,   // delta buckets, cross-partition labels updated at once
   SOLVE_BUFFERED = 1,  // delta buckets, cross-partition updates buffered per head
-  SOLVE_HEAP = 2       // one vertex at a time from an LDS binary heap
+  SOLVE_HEAP = 2,      // one vertex at a time from an LDS binary heap
+  SOLVE_IDLE_PRUNE = 3 // delta buckets; idle workgroups prune (LOCAL Trishla)
 };
+constexpr int PRUNE_CHUNK = 64;  // vertices per idle-pruning ticket
 
 // ------------------------------------------------------------ atomics
 // Every datum that several workgroups write or read while a kernel runs is
@@ -208,7 +210,8 @@ struct Ctrl {
   uint32_t nunits;
   uint32_t ovf;     // a relaxation candidate did not fit the distance type
   unsigned long long window;  // bounded lag in dist units (DELTA_INF = none)
-  uint32_t pad[26];
+  int32_t prune_next;         // SOLVE_IDLE_PRUNE: next prune ticket
+  uint32_t pad[25];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl layout");
 
@@ -227,6 +230,10 @@ struct SolveArgs {
   unsigned long long window;      // bounded lag (copied to Ctrl::window)
   unsigned long long time_limit;  // wall-clock ticks
   int32_t auto_lag;               // > 0: single solve with DELTA_AUTO, window = lag * width
+  int32_t prune_tasks;            // SOLVE_IDLE_PRUNE: vertex chunks idle workgroups prune
+  uint32_t *keepbits;             //   one bit per arc of solve 0, 1 = kept
+  uint8_t *keep_out;              //   optional uint8[m] copy of the bits after the solve
+  int32_t desc_m0;                //   arcs of solve 0
   int32_t pad;
 };
 

@@ -12,6 +12,7 @@ hipError_t launch_init(const SolveArgs &a, int nsolves, int max_n, hipStream_t s
 hipError_t launch_auto_delta(const SolveArgs &a, int wtype, int nsolves, hipStream_t st);
 hipError_t launch_solve(const SolveArgs &a, int wtype, int bs, int mode, int grid,
                         hipStream_t st);
+hipError_t launch_keep_out(const SolveArgs &a, hipStream_t st);
 hipError_t launch_epilogue(const SolveArgs &a, int wtype, int nsolves, int max_n,
                            hipStream_t st);
 int solve_max_blocks_per_cu(int wtype, int bs, int mode);

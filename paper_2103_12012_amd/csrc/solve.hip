@@ -97,6 +97,64 @@ __device__ __forceinline__ bool xb_insert(int32_t *keys, unsigned long long *val
 
 constexpr int MAX_ROUNDS_PER_BATCH = 256;
 
+// Idle-time pruning (SOLVE_IDLE_PRUNE, Sec. III-B: processes without
+// messages use their idle time for Trishla).  A workgroup that finds no
+// active unit takes a ticket for PRUNE_CHUNK consecutive vertices and tests
+// every arc (u, x, W) of each: deleted when a middle vertex y of u's own
+// partition (LOCAL scope), y != u and y != x, has arcs (u, y, w1) and
+// (y, x, w2) with w1 + w2 < W.  The heads of u go into an LDS hash table;
+// the rows of u's middles are walked edge-parallel and every two-arc cost
+// is min-combined into its head's slot; then each arc of u is compared
+// with its head's least detour.  Rows with more than PT_SLOTS / 2 arcs or
+// more than PRUNE_MAX_WEDGES two-arc paths are left alone, which keeps a
+// ticket short: any subset of the LOCAL deletion set is a valid result
+// (a deleted arc is never tight, so distances and predecessors do not
+// change), and the solve ends as soon as no work is pending, whether or
+// not every ticket was taken.
+constexpr int PT_SLOTS = 2048;
+constexpr int PRUNE_MAX_WEDGES = 1 << 16;
+
+__device__ __forceinline__ uint32_t pt_hash(int x) { return ((uint32_t)x * 2654435761u) >> 21; }
+
+// Slot of key x in the table (inserted if absent); the table never fills
+// (at most PT_SLOTS / 2 keys).
+__device__ __forceinline__ int pt_insert(int32_t *keys, int x) {
+  uint32_t h = pt_hash(x);
+  for (int probe = 0; probe < PT_SLOTS; probe++) {
+    const int old = atomicCAS(&keys[h], -1, x);
+    if (old == -1 || old == x) return (int)h;
+    h = (h + 1) & (PT_SLOTS - 1);
+  }
+  return -1;
+}
+__device__ __forceinline__ int pt_find(const int32_t *keys, int x) {
+  uint32_t h = pt_hash(x);
+  for (int probe = 0; probe < PT_SLOTS; probe++) {
+    const int k = keys[h];
+    if (k == x) return (int)h;
+    if (k == -1) return -1;
+    h = (h + 1) & (PT_SLOTS - 1);
+  }
+  return -1;
+}
+// Two-arc cost in a form that orders like the real sum: the integer sum, or
+// the double sum of two fp32 costs (as bits: nonnegative doubles order like
+// their bit patterns).  The double sum is exact unless the costs are more
+// than 29 binary orders apart, and then the rounding cannot change its
+// comparison with an fp32 cost.
+template <int WT>
+__device__ __forceinline__ unsigned long long pair_cost(uint32_t w1, uint32_t w2) {
+  if (WT == SSSP_W_U32) return (unsigned long long)w1 + w2;
+  const double d = (double)__uint_as_float(w1) + (double)__uint_as_float(w2);
+  return (unsigned long long)__double_as_longlong(d);
+}
+template <int WT>
+__device__ __forceinline__ bool pair_beats(unsigned long long c, uint32_t W) {
+  if (c == ~0ull) return false;
+  if (WT == SSSP_W_U32) return c < (unsigned long long)W;
+  return __longlong_as_double((long long)c) < (double)__uint_as_float(W);
+}
+
 // Binary min-heap in LDS for the heap mode (one thread operates on it):
 // the root is the least key; children of i are 2i+1 and 2i+2.
 constexpr int HCAP = 2048;
@@ -212,12 +270,24 @@ __global__ void k_init_global(SolveArgs a, int nsolves) {
     a.ctrl->status = 0;
     a.ctrl->nunits = (uint32_t)a.nunits;
     a.ctrl->ovf = 0u;
+    a.ctrl->prune_next = 0;
     a.ctrl->window = a.window;
   }
   if (a.stats) {
     uint32_t *s = reinterpret_cast<uint32_t *>(a.stats);
     for (int i = t; i < (int)(sizeof(sssp_stats) / 4); i += stride) s[i] = 0u;
   }
+  if (a.keepbits) {  // every arc starts kept
+    const int words = (a.desc_m0 + 31) / 32;
+    for (int i = t; i < words; i += stride) a.keepbits[i] = ~0u;
+  }
+}
+
+// Copies the keep bits of an idle-pruning solve to the caller's uint8 flags.
+__global__ void k_keep_out(SolveArgs a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int stride = gridDim.x * blockDim.x;
+  for (int e = t; e < a.desc_m0; e += stride) a.keep_out[e] = (a.keepbits[e >> 5] >> (e & 31)) & 1u;
 }
 
 // Per-solve init (blockIdx.y = solve): labels to +inf, empty inboxes, unit
@@ -370,6 +440,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
   constexpr int EPT = FCAP / BS;
   constexpr bool XBUF = MODE == SOLVE_BUFFERED;
   constexpr bool HEAP = MODE == SOLVE_HEAP;
+  constexpr bool IPRUNE = MODE == SOLVE_IDLE_PRUNE;
   static_assert(FCAP % BS == 0, "FCAP must be a multiple of the block size");
 
   __shared__ int32_t s_v[FCAP];       // claimed frontier vertices
@@ -398,6 +469,10 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
   __shared__ unsigned long long s_heap[HEAP ? HCAP : 1];     // heap mode: (dist, vertex) keys
   __shared__ int s_hn, s_hu, s_hr0, s_hr1;                   //   size; popped vertex and row
   __shared__ uint32_t s_hdu;                                 //   its distance
+  __shared__ int32_t s_pk[IPRUNE ? PT_SLOTS : 1];            // idle prune: heads of u
+  __shared__ unsigned long long s_pc[IPRUNE ? PT_SLOTS : 1]; //   least detour per head
+  __shared__ int s_ptask, s_pm;                              //   ticket; middles staged
+  __shared__ unsigned long long s_pruned, s_wedges;          //   arcs deleted; paths examined
 
   const int tid0 = threadIdx.x;
   if constexpr (XBUF) {
@@ -412,7 +487,11 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
     s_actk[i] = -1;
     s_actd[i] = 0xFFFFFFFFu;
   }
-  if (tid0 == 0) s_actn = 0;
+  if (tid0 == 0) {
+    s_actn = 0;
+    s_pruned = 0;
+    s_wedges = 0;
+  }
   Ctrl *ctrl = a.ctrl;
   if (tid0 == 0) {
     s_exit = ld_rlx(&ctrl->status) != 0;
@@ -552,6 +631,110 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
       }
       __syncthreads();
       if (s_exit) break;
+      if constexpr (IPRUNE) {
+        // no unit to settle: prune a chunk of vertices instead, if any is left
+        if (tid == 0) {
+          s_ptask = ld_rlx(&ctrl->prune_next) < a.prune_tasks ? aadd(&ctrl->prune_next, 1)
+                                                               : a.prune_tasks;
+          if (s_ptask < a.prune_tasks && s_solve != 0) {
+            s_solve = 0;
+            s_desc = a.desc[0];
+          }
+        }
+        __syncthreads();
+        const int task = uni(s_ptask);
+        if (task < a.prune_tasks) {
+          const int n = uni(s_desc.n);
+          const int m = uni(s_desc.m);
+          const int bsize = uni(s_desc.bsize);
+          const int32_t *__restrict__ row_ptr = uni_ptr(s_desc.row_ptr);
+          const int32_t *__restrict__ col = uni_ptr(s_desc.col);
+          const uint32_t *__restrict__ wgt = uni_ptr(s_desc.w);
+          const int u0 = task * PRUNE_CHUNK;
+          const int u1 = min(n, u0 + PRUNE_CHUNK);
+          for (int u = u0; u < u1; u++) {
+            const int r0 = row_ptr[u], r1 = row_ptr[u + 1];
+            const int deg = r1 - r0;
+            if (r0 < 0 || r1 > m || deg < 2 || deg > PT_SLOTS / 2) continue;  // uniform
+            const int pu = u / bsize;
+            for (int i = tid; i < PT_SLOTS; i += BS) {
+              s_pk[i] = -1;
+              s_pc[i] = ~0ull;
+            }
+            if (tid == 0) s_pm = 0;
+            __syncthreads();
+            // heads of u into the table; middles in u's partition staged
+            for (int i = tid; i < deg; i += BS) {
+              const int x = col[r0 + i];
+              if ((unsigned)x >= (unsigned)n) continue;
+              pt_insert(s_pk, x);
+              if (x != u && x / bsize == pu) {
+                const int y0 = row_ptr[x], y1 = row_ptr[x + 1];
+                const int k = atomicAdd(&s_pm, 1);
+                s_v[k] = x;
+                s_rs[k] = y0;
+                s_off[k] = (y0 < 0 || y1 < y0 || y1 > m) ? 0 : y1 - y0;
+                s_d[k] = wgt[r0 + i];
+              }
+            }
+            __syncthreads();
+            const int nm = uni(s_pm);  // <= deg <= FCAP
+            int degs[EPT];
+            int lsum = 0;
+#pragma unroll
+            for (int j = 0; j < EPT; j++) {
+              const int k = tid * EPT + j;
+              degs[j] = k < nm ? s_off[k] : 0;
+              lsum += degs[j];
+            }
+            int tot;
+            int run = block_excl_scan1<BS>(lsum, s_ws, &tot);
+#pragma unroll
+            for (int j = 0; j < EPT; j++) {
+              const int k = tid * EPT + j;
+              if (k < nm) s_off[k] = run;
+              run += degs[j];
+            }
+            __syncthreads();
+            tot = uni(tot);
+            if (tot == 0 || tot > PRUNE_MAX_WEDGES) continue;  // uniform
+            // every two-arc path u -> y -> x2: min-combine its cost into x2
+            for (int idx = tid; idx < tot; idx += BS) {
+              int lo = 0, hi = nm - 1;  // last k with s_off[k] <= idx
+              while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= idx) lo = mid;
+                else hi = mid - 1;
+              }
+              const int e2 = s_rs[lo] + (idx - s_off[lo]);
+              const int x2 = col[e2];
+              if (x2 == s_v[lo]) continue;  // the middle must differ from the head
+              const int slot = pt_find(s_pk, x2);
+              if (slot >= 0) atomicMin(&s_pc[slot], pair_cost<WT>(s_d[lo], wgt[e2]));
+            }
+            __syncthreads();
+            // each arc of u against its head's least detour
+            unsigned long long np = 0;
+            for (int i = tid; i < deg; i += BS) {
+              const int e = r0 + i;
+              const int x = col[e];
+              if ((unsigned)x >= (unsigned)n) continue;
+              const int slot = pt_find(s_pk, x);
+              if (slot >= 0 && pair_beats<WT>(s_pc[slot], wgt[e])) {
+                __hip_atomic_fetch_and(&a.keepbits[e >> 5], ~(1u << (e & 31)), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                np++;
+              }
+            }
+            np = wave_sum(np);
+            if (lane == 0 && np) atomicAdd(&s_pruned, np);
+            if (tid == 0) s_wedges += tot;
+            __syncthreads();
+          }
+          if (tid == 0) s_idle = 0;
+          continue;
+        }
+      }
       for (int k = 0; k < (1 << s_idle); k++) __builtin_amdgcn_s_sleep(16);
       continue;
     }
@@ -953,7 +1136,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
         for (int k0 = 0; k0 < cur_cnt; k0 += BS * 4) {
           unsigned long long lab[4];
           int rs[4], re[4];
-  #pragma unroll
+#pragma unroll
           for (int j = 0; j < 4; j++) {
             const int k = k0 + j * BS + tid;
             if (k < cur_cnt) {
@@ -965,7 +1148,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
               re[j] = row_ptr[u + 1];
             }
           }
-  #pragma unroll
+#pragma unroll
           for (int j = 0; j < 4; j++) {
             const int k = k0 + j * BS + tid;
             if (k < cur_cnt) {
@@ -984,7 +1167,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
         __syncthreads();
         int degs[EPT];
         int lsum = 0;
-  #pragma unroll
+#pragma unroll
         for (int j = 0; j < EPT; j++) {
           const int k = tid * EPT + j;
           degs[j] = k < cur_cnt ? s_off[k] : 0;
@@ -992,7 +1175,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
         }
         int tot;
         int run = block_excl_scan1<BS>(lsum, s_ws, &tot);  // s_ws reused after later barriers
-  #pragma unroll
+#pragma unroll
         for (int j = 0; j < EPT; j++) {
           const int k = tid * EPT + j;
           if (k < cur_cnt) s_off[k] = run;
@@ -1008,7 +1191,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
           int e[U], v[U];
           uint32_t du[U], wv[U], nd[U];
           bool act[U];
-  #pragma unroll
+#pragma unroll
           for (int j = 0; j < U; j++) {
             const int idx = b0 + j * BS + tid;
             act[j] = idx < tot;
@@ -1030,16 +1213,26 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
               du[j] = s_d[lo];
             }
           }
-  #pragma unroll
+          uint32_t kb[U];
+#pragma unroll
           for (int j = 0; j < U; j++)
             if (act[j]) {
               v[j] = col[e[j]];
               wv[j] = wgt[e[j]];
+              // arcs deleted by idle-time pruning are not relaxed (a plain
+              // load: a stale bit only relaxes a deleted arc, which is harmless)
+              if constexpr (IPRUNE) kb[j] = a.keepbits[e[j] >> 5];
             }
           unsigned long long pk[U], cur[U];
-  #pragma unroll
+#pragma unroll
           for (int j = 0; j < U; j++) {
             if (!act[j]) continue;
+            if constexpr (IPRUNE) {
+              if (!((kb[j] >> (e[j] & 31)) & 1u)) {
+                act[j] = false;
+                continue;
+              }
+            }
             if ((unsigned)v[j] >= (unsigned)n) {
               set_status(&ctrl->status, SSSP_ERR_CSR);
               act[j] = false;
@@ -1050,8 +1243,8 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
             if (ovf) {
               // a candidate that does not fit is no shorter path to anything
               // that fits: skip it.  Whether a final distance overflowed is
-              // decided after the fixed point (k_overflow_check); this flag
-              // only says that the check has to look.
+              // decided after the fixed point (in k_epilogue); this flag only
+              // says that the check has to look.
               st_rlx(&ctrl->ovf, 1u);
               act[j] = false;
               continue;
@@ -1066,13 +1259,13 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
           if constexpr (XBUF) {
             // cross-partition candidates that beat the current label wait in
             // the LDS buffer (applied once per distinct head at the flush)
-  #pragma unroll
+#pragma unroll
             for (int j = 0; j < U; j++)
               if (act[j] && pk[j] < cur[j] && v[j] / bsize != part &&
                   xb_insert(s_xbk, s_xbv, &s_xbn, v[j], pk[j]))
                 act[j] = false;
           }
-  #pragma unroll
+#pragma unroll
           for (int j = 0; j < U; j++) {
             if (act[j] && pk[j] < cur[j]) cur[j] = amin(&label[v[j]], pk[j]);
             else act[j] = false;
@@ -1080,7 +1273,7 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
           // lowered distances: same partition and same bucket -> next round in
           // LDS; otherwise -> the owner's inbox bit
           bool inbox[U];
-  #pragma unroll
+#pragma unroll
           for (int j = 0; j < U; j++) {
             inbox[j] = false;
             if (!act[j] || (uint32_t)(cur[j] >> 32) <= nd[j]) {
@@ -1108,10 +1301,10 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
             }
           }
           uint32_t ob[U];
-  #pragma unroll
+#pragma unroll
           for (int j = 0; j < U; j++)
             if (inbox[j]) ob[j] = aor(&dirty[v[j] >> 5], 1u << (v[j] & 31));
-  #pragma unroll
+#pragma unroll
           for (int j = 0; j < U; j++) {
             if (!inbox[j] || ((ob[j] >> (v[j] & 31)) & 1u)) continue;  // already pending
             nnew++;
@@ -1265,6 +1458,12 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
     __syncthreads();
     stay = s_stay;
   }
+  if constexpr (IPRUNE) {
+    if (threadIdx.x == 0 && a.stats && s_wedges) {
+      stat_add(&a.stats->edges_pruned, s_pruned);
+      stat_add(&a.stats->wedges, s_wedges);
+    }
+  }
   if (threadIdx.x == 0 && a.stats && st_batches) {
     stat_add(&a.stats->edges_relaxed, st_tot);
     stat_add(&a.stats->label_updates, st_upd);
@@ -1409,7 +1608,8 @@ hipError_t launch_auto_delta(const SolveArgs &a, int wtype, int nsolves, hipStre
 }
 
 hipError_t launch_init(const SolveArgs &a, int nsolves, int max_n, hipStream_t st) {
-  int gb = (a.nabw + 255) / 256;
+  const int kwords = a.keepbits ? (a.desc_m0 + 31) / 32 : 0;
+  int gb = ((kwords > a.nabw ? kwords : a.nabw) + 255) / 256;
   gb = gb < 1 ? 1 : (gb > 256 ? 256 : gb);
   hipLaunchKernelGGL(k_init_global, dim3(gb), dim3(256), 0, st, a, nsolves);
   hipError_t e = hipGetLastError();
@@ -1435,6 +1635,8 @@ static hipError_t solve_kernel_mode(int mode, const SolveArgs *a, int grid, hipS
                                     int *per_cu) {
   if (mode == SOLVE_BUFFERED) return solve_kernel_op<WT, BS, SOLVE_BUFFERED>(a, grid, st, per_cu);
   if (mode == SOLVE_HEAP) return solve_kernel_op<WT, BS, SOLVE_HEAP>(a, grid, st, per_cu);
+  if (mode == SOLVE_IDLE_PRUNE)
+    return solve_kernel_op<WT, BS, SOLVE_IDLE_PRUNE>(a, grid, st, per_cu);
   return solve_kernel_op<WT, BS, SOLVE_BUCKETS>(a, grid, st, per_cu);
 }
 
@@ -1458,6 +1660,13 @@ int solve_max_blocks_per_cu(int wtype, int bs, int mode) {
       wtype == SSSP_W_U32 ? solve_kernel_bs<SSSP_W_U32>(bs, mode, nullptr, 0, nullptr, &nb)
                           : solve_kernel_bs<SSSP_W_F32>(bs, mode, nullptr, 0, nullptr, &nb);
   return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
+hipError_t launch_keep_out(const SolveArgs &a, hipStream_t st) {
+  int blocks = (a.desc_m0 + 255) / 256;
+  blocks = blocks < 1 ? 1 : (blocks > 2048 ? 2048 : blocks);
+  hipLaunchKernelGGL(k_keep_out, dim3(blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_epilogue(const SolveArgs &a, int wtype, int nsolves, int max_n,

@@ -23,7 +23,7 @@ HEADER = os.path.join(_HERE, "..", "include", "sssp.h")
 
 W_U32, W_F32 = 0, 1
 F_VALIDATE, F_SYNC, F_PRUNE_LOCAL, F_NO_AUTOTUNE = 1, 2, 4, 8
-F_BUFFER_CROSS, F_LOCAL_HEAP = 16, 32
+F_BUFFER_CROSS, F_LOCAL_HEAP, F_IDLE_PRUNE = 16, 32, 64
 
 ERRORS = {
     0: "SSSP_OK", -1: "SSSP_ERR_ARG", -2: "SSSP_ERR_SOURCE", -3: "SSSP_ERR_CSR",
@@ -53,7 +53,7 @@ class Opts(ctypes.Structure):
                 ("wg_size", ctypes.c_int32), ("num_workgroups", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("lag", ctypes.c_int32), ("event_start", ctypes.c_void_p),
-                ("event_stop", ctypes.c_void_p)]
+                ("event_stop", ctypes.c_void_p), ("keep_out", ctypes.c_void_p)]
 
 
 STATS_FIELDS = ["edges_relaxed", "label_updates", "cross_updates", "vertices_expanded",
@@ -153,10 +153,11 @@ def _csr(row_ptr, col, w) -> CSR:
 
 def make_opts(delta=0.0, num_partitions=0, wg_size=0, num_workgroups=0, max_rounds=0,
               validate=True, sync=False, local=False, no_autotune=False, events=None,
-              lag=0, buffer_cross=False, local_heap=False) -> Opts:
+              lag=0, buffer_cross=False, local_heap=False, idle_prune=False) -> Opts:
     flags = (F_VALIDATE if validate else 0) | (F_SYNC if sync else 0) | \
             (F_PRUNE_LOCAL if local else 0) | (F_NO_AUTOTUNE if no_autotune else 0) | \
-            (F_BUFFER_CROSS if buffer_cross else 0) | (F_LOCAL_HEAP if local_heap else 0)
+            (F_BUFFER_CROSS if buffer_cross else 0) | (F_LOCAL_HEAP if local_heap else 0) | \
+            (F_IDLE_PRUNE if idle_prune else 0)
     o = Opts()
     o.delta = float(delta)
     o.num_partitions = int(num_partitions)
@@ -238,12 +239,18 @@ class Solver:
     def __init__(self, row_ptr, col, w, *, delta=0.0, num_partitions=0, wg_size=0,
                  num_workgroups=0, max_rounds=0, validate=True, want_pred=True,
                  stats=False, lag=0, no_autotune=False, buffer_cross=False,
-                 local_heap=False):
+                 local_heap=False, idle_prune=False, want_keep=False):
         self.g = _csr(row_ptr, col, w)
         self._keep = (row_ptr, col, w)
         self.opts = make_opts(delta, num_partitions, wg_size, num_workgroups, max_rounds,
                               validate=validate, lag=lag, no_autotune=no_autotune,
-                              buffer_cross=buffer_cross, local_heap=local_heap)
+                              buffer_cross=buffer_cross, local_heap=local_heap,
+                              idle_prune=idle_prune)
+        # idle pruning: the keep flags of the arcs (1 kept, 0 deleted during the solve)
+        self.keep = None
+        if idle_prune and want_keep:
+            self.keep = torch.empty(max(self.g.m, 1), dtype=torch.uint8, device=col.device)
+            self.opts.keep_out = self.keep.data_ptr()
         dev = col.device
         self.col_device = dev
         n = self.g.n
@@ -294,7 +301,7 @@ class BatchSolver:
 
     def __init__(self, graphs, solve_graph, solve_source, *, delta=0.0, num_partitions=0,
                  wg_size=0, num_workgroups=0, validate=False, want_pred=True, stats=False,
-                 buffer_cross=False, local_heap=False):
+                 buffer_cross=False, local_heap=False, idle_prune=False):
         self._keep = graphs
         self.gs = (CSR * len(graphs))(*[_csr(*g) for g in graphs])
         wdt = graphs[0][2].dtype
@@ -310,7 +317,7 @@ class BatchSolver:
         self.total = tot
         self.opts = make_opts(delta, num_partitions, wg_size, num_workgroups,
                               validate=validate, buffer_cross=buffer_cross,
-                              local_heap=local_heap)
+                              local_heap=local_heap, idle_prune=idle_prune)
         self.dist = torch.empty(tot, dtype=wdt, device=dev)
         self.pred = torch.empty(tot, dtype=torch.int32, device=dev) if want_pred else None
         self.pred_edge = torch.empty(tot, dtype=torch.int32, device=dev)

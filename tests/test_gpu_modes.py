@@ -181,3 +181,77 @@ def test_heap_flag_excludes_buffering():
     with pytest.raises(S.SSSPError) as ei:
         gpu_solve(g, 0, local_heap=True, buffer_cross=True)
     assert ei.value.code == -1
+
+
+# ------------------------------------------------ idle-time pruning (LOCAL)
+def idle_prune_solve(g, s, P, **kw):
+    S = sssp_mod()
+    rp, c, w = dev(g)
+    solver = S.Solver(rp, c, w, num_partitions=P, idle_prune=True, want_keep=True, stats=True,
+                      **kw)
+    dist, pred, pe = solver(s, sync=True)
+    st = solver.stats.read()
+    assert st["status"] == 0 and st["num_partitions"] == P
+    res = (dist.cpu().numpy().view(np.uint32) if g.w.dtype == np.uint32 else dist.cpu().numpy(),
+           pred.cpu().numpy(), pe.cpu().numpy())
+    return res, solver.keep[:g.m].cpu().numpy(), st
+
+
+def check_idle_prune(g, s, P, **kw):
+    """Distances and predecessors equal the oracle's on the unpruned graph,
+    and every arc deleted during the solve is in the oracle's LOCAL
+    deletion set for the same partitions."""
+    res, keep, st = idle_prune_solve(g, s, P, **kw)
+    assert_solve_parity(g, s, res)
+    local_del = oracle.trishla(g.row_ptr, g.col, g.w, local_scope=True, nparts=P) == 0
+    deleted = keep == 0
+    assert not np.any(deleted & ~local_del), np.nonzero(deleted & ~local_del)[0][:10]
+    assert int(deleted.sum()) == st["edges_pruned"]
+    return int(deleted.sum()), int(local_del.sum())
+
+
+@pytest.mark.parametrize("case", ["c1", "rmat14", "rmat13_f32", "rmat14_wg256"])
+def test_idle_prune_parity_and_subset(case):
+    if case == "c1":
+        g, s, P, kw = gen.uniform(4096, 32768, seed=1), 0, 4, {}
+    elif case == "rmat13_f32":
+        g = gen.rmat(13, 13, weight="f32", wlo=0.1, whi=3.0)
+        s, P, kw = int(gen.random_sources(g, 1, 13)[0]), 8, {}
+    else:
+        g = gen.rmat(14, 14)
+        s, P = int(gen.random_sources(g, 1, 14)[0]), 16
+        kw = dict(wg_size=256, num_workgroups=64) if case.endswith("wg256") else {}
+    check_idle_prune(g, s, P, **kw)
+
+
+def test_idle_prune_runs_while_the_frontier_is_elsewhere():
+    """Partition 0 holds a 4096-vertex path from the source (one vertex per
+    round, so the solve takes many batches); partition 1 is a dense random
+    cluster reached only through the path's end.  Idle workgroups prune
+    partition 1 long before the solve gets there: arcs are deleted, all of
+    them in the LOCAL deletion set, and the result is exact."""
+    rng = np.random.default_rng(12)
+    B = 4096
+    pu, pv = np.arange(B - 1), np.arange(1, B)
+    m1 = 64 * B
+    cu = rng.integers(B, 2 * B, size=m1)
+    cv = rng.integers(B, 2 * B, size=m1)
+    ok = cu != cv
+    u = np.concatenate([pu, [B - 1], cu[ok]])
+    v = np.concatenate([pv, [B], cv[ok]])
+    w = np.concatenate([np.ones(B, np.uint32), rng.integers(1, 101, size=int(ok.sum()))
+                        .astype(np.uint32)])
+    g = gen.from_arcs(2 * B, u, v, w)
+    pruned, local = check_idle_prune(g, 0, 2, lag=-1)
+    assert local > 0 and pruned > 0, (pruned, local)
+
+
+def test_idle_prune_refused_with_other_modes_and_batches():
+    S = sssp_mod()
+    g = gen.uniform(64, 256, 2)
+    with pytest.raises(S.SSSPError) as ei:
+        gpu_solve(g, 0, idle_prune=True, local_heap=True)
+    assert ei.value.code == -1
+    with pytest.raises(S.SSSPError) as ei:
+        S.solve_batch([dev(g)], [0], [0], idle_prune=True)
+    assert ei.value.code == -1
