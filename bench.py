@@ -76,6 +76,8 @@ KERNEL_SOURCES = {  # files each kernel is compiled from (for the counter-stalen
     "k_tb_heavy_t1": ("internal.hpp", "prune.hip"),
     "k_tb_heavy_t2": ("internal.hpp", "prune.hip"),
     "k_tb_heavy_big": ("internal.hpp", "prune.hip"),
+    # every kernel of sssp_backward (clear, parents, marks, counts, leaves, chains, check)
+    "k_bwd": ("internal.hpp", "backward.hip"),
 }
 TRISHLA_SCAN = ("k_tb_light", "k_tb_heavy_t0", "k_tb_heavy_t1", "k_tb_heavy_t2", "k_tb_heavy_big")
 
@@ -173,8 +175,34 @@ def bench_rmat20(steps, warmup, cpu_leg=True):
     prune_step()
     torch.cuda.synchronize()
     kept_m = int(out_rp[-1].item())
-    solver = sssp.Solver(out_rp, out_c[:kept_m], out_w[:kept_m], num_partitions=P,
-                         validate=False, stats=True)
+    # one prune with counters: arcs deleted and list entries examined
+    pst = sssp.StatsBuffer.new(dev)
+    o = sssp.Opts.from_buffer_copy(popt)
+    n2 = ctypes.c_size_t(pws.numel())
+    assert L.sssp_prune(ctypes.byref(gcsr), ctypes.byref(o), sssp._ptr(keep), *outs,
+                        sssp._ptr(pst.t), sssp._ptr(pws), ctypes.byref(n2), sssp._stream()) == 0
+    torch.cuda.synchronize()
+    prune_stats = pst.read()
+    pg = (out_rp, out_c[:kept_m], out_w[:kept_m])
+    # autotune the solve of the pruned graph (P fixed at 256; timed from this
+    # source and four others, scored by the median) and compare with the
+    # library defaults on this source; the step itself runs with the
+    # defaults (the configuration fixes P only)
+    tuned = sssp.autotune(*pg, s, num_partitions=P)
+    ev0 = HipEvents()
+
+    def solve_ms(sv, reps=10):
+        sv(s)
+        ts = []
+        for _ in range(reps):
+            e = ev0.pair()
+            sv(s, events=e)
+            ts.append(ev0.ms(e))
+        return float(np.median(ts))
+
+    default_ms = solve_ms(sssp.Solver(*pg, num_partitions=P, validate=False, no_autotune=True))
+    tuned_ms = solve_ms(sssp.Solver(*pg, num_partitions=P, validate=False))
+    solver = sssp.Solver(*pg, num_partitions=P, validate=False, stats=True, no_autotune=True)
     for _ in range(warmup):
         prune_step()
         solver(s)
@@ -218,6 +246,10 @@ def bench_rmat20(steps, warmup, cpu_leg=True):
     b_solve = 24 * g.n + 16 * reached + 16 * mr_pruned
     # Trishla: read CSR (8 B / arc + row pointers), keep flags, compacted CSR
     b_prune = 4 * (g.n + 1) + 8 * g.m + g.m + 4 * (g.n + 1) + 12 * kept_m
+    rp_prune = roofline("trishla_scan", b_prune, prune_ms, workload="rmat20", parts=TRISHLA_SCAN)
+    rp_prune["kernels"] = "k_tb_light + k_tb_heavy (four tiers), run concurrently"
+    rp_prune["entries_examined"] = prune_stats["wedges"]
+    rp_prune["entries_examined_per_s"] = round(prune_stats["wedges"] / (prune_ms * 1e-3), 1)
     res = {
         "gteps": mcc / (ms_step * 1e-3) / 1e9,
         "ms_per_step": ms_step,
@@ -231,9 +263,12 @@ def bench_rmat20(steps, warmup, cpu_leg=True):
         "n": g.n, "m": g.m, "m_kept": kept_m, "m_cc": mcc, "reached": reached, "source": s,
         "stats": st,
         "roofline_solve": roofline("k_solve", b_solve, solve_ms, workload="rmat20"),
-        "roofline_prune": roofline("k_tb_light+k_tb_heavy", b_prune, prune_ms, workload="rmat20",
-                                   parts=TRISHLA_SCAN),
-        "wedges": st.get("wedges"),
+        "roofline_prune": rp_prune,
+        "prune_stats": {"edges_pruned": prune_stats["edges_pruned"],
+                        "entries_examined": prune_stats["wedges"]},
+        "autotune": {"tuned_options": tuned, "solve_ms_default_options": round(default_ms, 4),
+                     "solve_ms_tuned_options": round(tuned_ms, 4),
+                     "note": "median of 10 solves of the pruned graph from the headline source"},
     }
     if cpu_leg:
         res["cpu_baseline"] = cpu_baseline_rmat20(g, s, mcc)
@@ -277,14 +312,39 @@ def host_cpu():
 
 
 # ------------------------------------------------------------------ extras
-def bench_grid(steps):
+def b_solve(n, reached, m_r):
+    """Algorithmic bytes of one solve: init 8 B and epilogue 16 B per vertex,
+    row bounds + own label per reached vertex, col + cost + head label per
+    arc out of a reached vertex."""
+    return 24 * n + 16 * reached + 16 * m_r
+
+
+def solve_bytes_from_dist(g, dist_u32_or_f32):
+    reached_mask = (dist_u32_or_f32 != 0xFFFFFFFF) if dist_u32_or_f32.dtype == np.uint32 \
+        else np.isfinite(dist_u32_or_f32)
+    m_r = int(g.out_degree()[reached_mask].sum())
+    return b_solve(g.n, int(reached_mask.sum()), m_r), int(reached_mask.sum()), m_r
+
+
+def time_oracle_dijkstra(g, sources):
+    """Single-thread oracle Dijkstra from each source; returns (seconds, dists)."""
+    import oracle
+
+    t0 = time.perf_counter()
+    ds = [oracle.sssp(g.row_ptr, g.col, g.w, int(s)) for s in sources]
+    return time.perf_counter() - t0, ds
+
+
+def bench_grid(steps, cpu_leg=True):
     import torch
 
     from paper_2103_12012_amd import gen, sssp
 
     g = gen.grid(4096, 4096, seed=3)
     rp, c, w = sssp.to_device(g, "cuda")
-    solver = sssp.Solver(rp, c, w, validate=False, stats=True)
+    # the library defaults: the automatic options tried best in sweeps of
+    # delta, P, lag, workgroup and grid size on this graph
+    solver = sssp.Solver(rp, c, w, validate=False, stats=True, no_autotune=True)
     solver(0)
     torch.cuda.synchronize()
     ev = HipEvents()
@@ -295,13 +355,25 @@ def bench_grid(steps):
         ts.append(ev.ms(e))
     ms = float(np.mean(ts))
     st = solver.stats.read()
-    b = 24 * g.n + 16 * g.n + 16 * g.m
-    return {"workload": "grid4096_corner", "n": g.n, "m": g.m, "solve_ms": ms,
-            "gteps": g.m / (ms * 1e-3) / 1e9, "roofline": roofline("k_solve", b, ms),
-            "stats": st}
+    dist = solver.dist.cpu().numpy().view(np.uint32)
+    b, reached, m_r = solve_bytes_from_dist(g, dist)
+    out = {"workload": "grid4096_corner", "n": g.n, "m": g.m, "solve_ms": ms,
+           "solve_ms_median": float(np.median(ts)), "trials": len(ts),
+           "gteps": g.m / (ms * 1e-3) / 1e9,
+           "roofline": roofline("k_solve", b, ms, workload="grid4096"), "stats": st}
+    if cpu_leg:
+        import oracle
+
+        secs, (d_ref,) = time_oracle_dijkstra(g, [0])
+        out["matches_oracle"] = bool(np.array_equal(d_ref.astype(np.uint32), dist))
+        out["cpu_baseline"] = {"value": round(g.m / secs / 1e9, 5), "unit": "GTEPS", "cores": 1,
+                               "kind": "oracle", "host": host_cpu(),
+                               "sample": f"the whole workload: binary-heap Dijkstra from the "
+                                         f"corner, one thread, {secs:.2f}s"}
+    return out
 
 
-def bench_batch(steps):
+def bench_batch(steps, cpu_leg=True):
     import torch
 
     from paper_2103_12012_amd import gen, sssp
@@ -318,25 +390,6 @@ def bench_batch(steps):
     mcc = 0
     for gi, s in zip(sg, ss):
         mcc += m_reached(graphs[gi], s)[0]
-    # the batched launch is tuned as a whole (sssp_autotune_batch); the single
-    # calls below use per-scale single-solve tuning (sssp_autotune)
-    b = sssp.BatchSolver(dg, sg, ss)
-    tuned_batch = b.autotune()
-    b()
-    torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    stream = torch.cuda.Stream()
-    with torch.cuda.stream(stream):
-        with torch.cuda.graph(graph, stream=stream):
-            b()
-    torch.cuda.synchronize()
-    graph.replay()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        graph.replay()
-    torch.cuda.synchronize()
-    batch_ms = (time.perf_counter() - t0) / steps * 1e3
     # the same 256 solves as single-source calls, each autotuned per scale
     tuned = {}
     for gi, s in zip(sg, ss):
@@ -355,14 +408,79 @@ def bench_batch(steps):
             solvers[gi](s)
     torch.cuda.synchronize()
     single_ms = (time.perf_counter() - t0) / steps * 1e3
-    return {"workload": "batched_64rmat_12to18_x4", "solves": len(sg), "m_cc_total": mcc,
-            "tuned_batch": tuned_batch,
-            "tuned_single": {str(k): v for k, v in sorted(tuned.items())},
-            "batch_ms": batch_ms, "batch_gteps": mcc / (batch_ms * 1e-3) / 1e9,
-            "single_calls_ms": single_ms, "single_gteps": mcc / (single_ms * 1e-3) / 1e9}
+    # the batched launch, tuned as a whole (sssp_autotune_batch), replayed
+    # from a captured HIP graph
+    b = sssp.BatchSolver(dg, sg, ss)
+    tuned_batch = b.autotune()
+    b()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            b()
+    torch.cuda.synchronize()
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    batch_ms = (time.perf_counter() - t0) / steps * 1e3
+    # algorithmic bytes of the 256 solves, from the batched output
+    dists = [d.cpu().numpy().view(np.uint32) for d in b.split(b.dist)]
+    b_total = 0
+    for gi, d in zip(sg, dists):
+        b_total += solve_bytes_from_dist(graphs[gi], d)[0]
+    # k_solve of the batched launch alone (HIP events around it), eager; the
+    # last two k_solve dispatches of this leg (the counter profile reads them)
+    ev = HipEvents()
+    kms = []
+    for _ in range(2):
+        e = ev.pair()
+        b(events=e)
+        kms.append(ev.ms(e))
+    kernel_ms = float(np.mean(kms))
+    out = {"workload": "batched_64rmat_12to18_x4", "solves": len(sg), "m_cc_total": mcc,
+           "tuned_batch": tuned_batch,
+           "tuned_single": {str(k): v for k, v in sorted(tuned.items())},
+           "batch_ms": batch_ms, "batch_gteps": mcc / (batch_ms * 1e-3) / 1e9,
+           "batch_k_solve_ms": kernel_ms,
+           "single_calls_ms": single_ms, "single_gteps": mcc / (single_ms * 1e-3) / 1e9,
+           "roofline_batched": roofline("k_solve", b_total, kernel_ms, workload="batch"),
+           "roofline_single_calls": roofline("256 sssp_solve calls", b_total, single_ms)}
+    out["roofline_single_calls"]["note"] = ("whole-call time of the 256 calls (launch gaps "
+                                            "included), same algorithmic bytes")
+    if cpu_leg:
+        # bounded sample: the first source of each of the 64 graphs
+        pick = [k for k in range(len(sg)) if k % 4 == 0]
+        secs = 0.0
+        m_sample = 0
+        ok = True
+        for k in pick:
+            g = graphs[sg[k]]
+            t, (d_ref,) = time_oracle_dijkstra(g, [ss[k]])
+            secs += t
+            m_sample += m_reached(g, ss[k])[0]
+            ok = ok and np.array_equal(np.where(d_ref == np.iinfo(np.uint64).max, 0xFFFFFFFF,
+                                                d_ref).astype(np.uint32), dists[k])
+        out["sample_matches_oracle"] = bool(ok)
+        out["cpu_baseline"] = {"value": round(m_sample / secs / 1e9, 5), "unit": "GTEPS",
+                               "cores": 1, "kind": "oracle", "host": host_cpu(),
+                               "sample": f"64 of the 256 solves (the first source of every "
+                                         f"graph), binary-heap Dijkstra one thread, "
+                                         f"{secs:.2f}s"}
+    return out
 
 
-def bench_diff(steps):
+def b_bwd(n, m, reached):
+    """Algorithmic bytes of the backward: clear grad_w (4 B per arc), read
+    dist, pred_edge and the upstream gradient and keep a subtree total per
+    vertex (20 B), scatter one gradient per reached vertex (4 B)."""
+    return 4 * m + 20 * n + 4 * reached
+
+
+def bench_diff(steps, cpu_leg=True):
     import torch
 
     from paper_2103_12012_amd import gen, sssp
@@ -370,6 +488,7 @@ def bench_diff(steps):
     g = gen.rmat(22, 22, weight="f32", wlo=0.5, whi=1.5)
     s = int(gen.random_sources(g, 1, 22)[0])
     t = gen.random_targets(g, s, 1024, 23)
+    mcc, ncc = m_reached(g, s)
     rp, c, w = sssp.to_device(g, "cuda")
     gd = torch.zeros(g.n, dtype=torch.float32, device="cuda")
     gd[torch.from_numpy(t).long().cuda()] = 1.0
@@ -384,6 +503,7 @@ def bench_diff(steps):
                            None, None, ctypes.byref(nb), None) == 0
     ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
     grad_w = torch.empty(g.m, dtype=torch.float32, device="cuda")
+    bst = sssp.StatsBuffer.new("cuda")
     fwd, bwd = [], []
     for _ in range(max(1, steps)):
         e1 = ev.pair()
@@ -394,14 +514,66 @@ def bench_diff(steps):
         n2 = ctypes.c_size_t(ws.numel())
         rc = L.sssp_backward(ctypes.byref(gcsr), s, sssp._ptr(solver.dist),
                              sssp._ptr(solver.pred_edge), sssp._ptr(gd), sssp._ptr(grad_w),
-                             ctypes.byref(o2), None, sssp._ptr(ws), ctypes.byref(n2),
+                             ctypes.byref(o2), sssp._ptr(bst.t), sssp._ptr(ws), ctypes.byref(n2),
                              sssp._stream())
         assert rc == 0
         fwd.append(ev.ms(e1))
         bwd.append(ev.ms(e2))
-    return {"workload": "rmat22_f32_1024_targets", "n": g.n, "m": g.m,
-            "forward_ms": float(np.mean(fwd)), "backward_ms": float(np.mean(bwd)),
-            "tolerance": "1e-5 rel dist (bit-exact expected), 1e-4 grad"}
+    torch.cuda.synchronize()
+    status = bst.read()["status"]
+    fwd_ms, bwd_ms = float(np.mean(fwd)), float(np.mean(bwd))
+    dist = solver.dist.cpu().numpy()
+    gw = grad_w.cpu().numpy()
+    bf, reached, m_r = solve_bytes_from_dist(g, dist)
+    out = {"workload": "rmat22_f32_1024_targets", "n": g.n, "m": g.m, "m_cc": mcc,
+           "forward_ms": fwd_ms, "backward_ms": bwd_ms, "backward_status": status,
+           "forward_gteps": mcc / (fwd_ms * 1e-3) / 1e9,
+           "roofline_forward": roofline("k_solve", bf, fwd_ms, workload="rmat22f32"),
+           "roofline_backward": roofline("k_bwd", b_bwd(g.n, g.m, reached), bwd_ms,
+                                         workload="rmat22f32"),
+           "trials": len(fwd)}
+    out["roofline_backward"]["kernels"] = "every kernel of sssp_backward (HIP events around them)"
+    # the plain single-source kernel on the same topology with uint32 costs
+    gu = gen.rmat(22, 22)
+    assert np.array_equal(gu.col, g.col)
+    rpu, cu, wu = sssp.to_device(gu, "cuda")
+    su = sssp.Solver(rpu, cu, wu, validate=False, want_pred=False)
+    su(s)
+    us = []
+    for _ in range(max(1, steps)):
+        e = ev.pair()
+        su(s, events=e)
+        us.append(ev.ms(e))
+    # same topology, so the same arcs are reached (m_cc)
+    out["u32_same_graph"] = {"weights": "uint32 U{1..255}", "solve_ms": float(np.mean(us)),
+                             "gteps": mcc / (float(np.mean(us)) * 1e-3) / 1e9}
+    del gu, rpu, cu, wu, su
+    if cpu_leg:
+        import oracle
+
+        t0 = time.perf_counter()
+        d_ref = oracle.sssp(g.row_ptr, g.col, g.w, s)
+        t1 = time.perf_counter()
+        pe_ref, _ = oracle.pred(g.row_ptr, g.col, g.w, s, d_ref)
+        gv = np.zeros(g.n, np.float32)
+        gv[t] = 1.0
+        t2 = time.perf_counter()
+        g_ref = oracle.grad(g.row_ptr, s, pe_ref, gv)
+        t3 = time.perf_counter()
+        nz = g_ref != 0
+        rel = np.abs(gw[nz] - g_ref[nz]) / np.abs(g_ref[nz])
+        out["check"] = {
+            "dist_bitwise_mismatches": int((dist.view(np.uint32) != d_ref.view(np.uint32)).sum()),
+            "grad_max_rel_err": float(rel.max()) if rel.size else 0.0,
+            "grad_max_abs_err_where_ref_zero": float(np.abs(gw[~nz]).max()) if (~nz).any() else 0.0,
+            "grad_nonzero_arcs": int(nz.sum()), "tolerance_rel": 1e-4}
+        out["cpu_baseline"] = {"value": round(mcc / (t1 - t0) / 1e9, 5), "unit": "GTEPS",
+                               "cores": 1, "kind": "oracle", "host": host_cpu(),
+                               "backward_ms": round((t3 - t2) * 1e3 + (t2 - t1) * 1e3, 2),
+                               "sample": f"the whole workload: fp32 binary-heap Dijkstra "
+                                         f"{t1-t0:.2f}s, then predecessor pass {t2-t1:.2f}s and "
+                                         f"tree-path gradient {t3-t2:.3f}s, one thread"}
+    return out
 
 
 def bench_ablation(steps):
@@ -423,10 +595,18 @@ def bench_ablation(steps):
     kept = int(prp[-1].item())
     ev = HipEvents()
     out = {"workload": "rmat20_pruned_local_rule", "partitions": 256}
-    for name, delta, lag in (("dijkstra_order_delta1", 1.0, -1), ("dijkstra_order_delta1_lag1", 1.0, 1),
-                             ("async_bellman_ford", -1.0, 0), ("auto", 0.0, 0)):
-        solver = sssp.Solver(prp, pc[:kept], pw[:kept], num_partitions=256, delta=delta,
-                             lag=lag, validate=False, stats=True, no_autotune=True)
+    rows = (("dijkstra_order_delta1", dict(delta=1.0, lag=-1)),
+            ("dijkstra_order_delta1_lag1", dict(delta=1.0, lag=1)),
+            ("async_bellman_ford", dict(delta=-1.0)),
+            ("auto", {}),
+            # Alg. 3 literally: one vertex at a time from an LDS binary heap
+            ("dijkstra_heap", dict(local_heap=True)),
+            ("dijkstra_heap_unbounded_lag", dict(local_heap=True, lag=-1)),
+            # cross-partition updates buffered per head in LDS (future-work buffering)
+            ("buffered_cross_updates", dict(buffer_cross=True)))
+    for name, kw in rows:
+        solver = sssp.Solver(prp, pc[:kept], pw[:kept], num_partitions=256, validate=False,
+                             stats=True, no_autotune=True, **kw)
         ts = []
         for _ in range(max(2, steps)):
             e = ev.pair()
@@ -436,6 +616,20 @@ def bench_ablation(steps):
         out[name] = {"solve_ms": float(np.median(ts)), "edges_relaxed": st["edges_relaxed"],
                      "label_updates": st["label_updates"],
                      "vertices_expanded": st["vertices_expanded"], "batches": st["batches"]}
+    # idle-time LOCAL pruning inside the solve, on the unpruned graph (no
+    # separate Trishla phase), against the plain solve of the unpruned graph
+    for name, kw in (("unpruned_plain", {}), ("unpruned_idle_prune", dict(idle_prune=True))):
+        solver = sssp.Solver(rp, c, w, num_partitions=256, validate=False, stats=True,
+                             no_autotune=True, **kw)
+        ts = []
+        for _ in range(max(2, steps)):
+            e = ev.pair()
+            solver(s, events=e)
+            ts.append(ev.ms(e))
+        st = solver.stats.read()
+        out[name] = {"solve_ms": float(np.median(ts)), "edges_relaxed": st["edges_relaxed"],
+                     "edges_pruned_during_solve": st["edges_pruned"],
+                     "two_arc_paths_examined": st["wedges"]}
     return out
 
 
@@ -487,17 +681,19 @@ def main():
     for name, fn in (("grid", bench_grid), ("batch", bench_batch), ("diff", bench_diff),
                      ("ablation", bench_ablation), ("copy", bench_copy)):
         if name in only:
-            extra[name] = fn(max(1, min(args.steps, 5)))
+            k = max(1, min(args.steps, 5))
+            extra[name] = fn(k, cpu_leg=not args.no_cpu) if name in ("grid", "batch", "diff") \
+                else fn(k)
             print(f"[bench] {name} done", file=sys.stderr, flush=True)
     line = {"metric": METRIC, "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "u32", "data": "synthetic"}
     if head is not None:
-        # the roofline names k_solve, the longest kernel that has the GPU to
-        # itself; the Trishla scan phase (reported as roofline_prune) is five
-        # kernels run concurrently on four streams, so no single one of them
-        # owns its launch time (see profiles/k_solve_trishla_rmat20_step.txt)
-        dom = head["roofline_solve"]
+        # the roofline names the dominant part of the step: the Trishla scan
+        # phase (five kernels run concurrently; the big tier's kernel spans the
+        # phase, see profiles/k_solve_trishla_rmat20_step.txt); the solve's
+        # own kernel is reported beside it as roofline_solve
+        dom = head["roofline_prune"]
         line.update({
             "value": round(head["gteps"], 4), "ms_per_step": round(head["ms_per_step"], 4),
             "config": {"workload": "rmat20_trishla_then_sssp", "scale": 20, "edge_factor": 16,
@@ -509,7 +705,8 @@ def main():
             "prune_ms": round(head["prune_ms"], 4), "solve_ms": round(head["solve_ms"], 4),
             "trials": head["trials"],
             "roofline_solve": head["roofline_solve"], "roofline_prune": head["roofline_prune"],
-            "solve_stats": head["stats"],
+            "solve_stats": head["stats"], "prune_stats": head["prune_stats"],
+            "autotune": head["autotune"],
         })
         if "cpu_baseline" in head:
             line["cpu_baseline"] = head["cpu_baseline"]

@@ -19,7 +19,7 @@ def test_autotune_then_solve(tmp_path):
     path = tmp_path / "tune.json"
     best = S.autotune(*d, s, cache_path=str(path))
     assert best["num_partitions"] >= 1 and best["wg_size"] in (256, 512)
-    assert best["delta"] == -1.0 or best["delta"] > 0
+    assert best["delta"] == -1.0 or best["delta"] >= 0  # 0 = the automatic width
     text = path.read_text()
     entries = json.loads(text)
     assert any("log2n=12" in e["key"] for e in entries)
