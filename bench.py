@@ -129,7 +129,7 @@ def roofline(name, bytes_alg, ms, bound="hbm", workload=None, parts=None):
 
 
 # ------------------------------------------------------------------ headline
-def bench_rmat20(steps, warmup, cpu_leg=True):
+def bench_rmat20(steps, warmup, cpu_leg=True, tune=True):
     import torch
 
     from paper_2103_12012_amd import gen, sssp
@@ -188,7 +188,6 @@ def bench_rmat20(steps, warmup, cpu_leg=True):
     # source and four others, scored by the median) and compare with the
     # library defaults on this source; the step itself runs with the
     # defaults (the configuration fixes P only)
-    tuned = sssp.autotune(*pg, s, num_partitions=P)
     ev0 = HipEvents()
 
     def solve_ms(sv, reps=10):
@@ -200,8 +199,17 @@ def bench_rmat20(steps, warmup, cpu_leg=True):
             ts.append(ev0.ms(e))
         return float(np.median(ts))
 
-    default_ms = solve_ms(sssp.Solver(*pg, num_partitions=P, validate=False, no_autotune=True))
-    tuned_ms = solve_ms(sssp.Solver(*pg, num_partitions=P, validate=False))
+    if tune:
+        tuned = sssp.autotune(*pg, s, num_partitions=P)
+        default_ms = solve_ms(sssp.Solver(*pg, num_partitions=P, validate=False,
+                                          no_autotune=True))
+        tuned_ms = solve_ms(sssp.Solver(*pg, num_partitions=P, validate=False))
+        autotune_res = {"tuned_options": tuned, "solve_ms_default_options": round(default_ms, 4),
+                        "solve_ms_tuned_options": round(tuned_ms, 4),
+                        "note": "median of 10 solves of the pruned graph from the headline "
+                                "source"}
+    else:
+        autotune_res = {"skipped": True}
     solver = sssp.Solver(*pg, num_partitions=P, validate=False, stats=True, no_autotune=True)
     for _ in range(warmup):
         prune_step()
@@ -266,9 +274,7 @@ def bench_rmat20(steps, warmup, cpu_leg=True):
         "roofline_prune": rp_prune,
         "prune_stats": {"edges_pruned": prune_stats["edges_pruned"],
                         "entries_examined": prune_stats["wedges"]},
-        "autotune": {"tuned_options": tuned, "solve_ms_default_options": round(default_ms, 4),
-                     "solve_ms_tuned_options": round(tuned_ms, 4),
-                     "note": "median of 10 solves of the pruned graph from the headline source"},
+        "autotune": autotune_res,
     }
     if cpu_leg:
         res["cpu_baseline"] = cpu_baseline_rmat20(g, s, mcc)
@@ -661,7 +667,10 @@ def main():
     ap.add_argument("--only", nargs="*", default=None,
                     help="subset of: rmat20 grid batch diff ablation copy (copy: counter "
                          "calibration, not part of the default run)")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
+    ap.add_argument("--skip-autotune", action="store_true",
+                    help="headline: skip the autotune comparison (counter runs: every solve "
+                         "of the leg then uses the default options)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (--gpus 1): the library has no multi-GPU path",
@@ -675,7 +684,8 @@ def main():
     extra = {}
     head = None
     if "rmat20" in only:
-        head = bench_rmat20(args.steps, args.warmup, cpu_leg=not args.no_cpu)
+        head = bench_rmat20(args.steps, args.warmup, cpu_leg=not args.no_cpu,
+                            tune=not args.skip_autotune)
         print(f"[bench] rmat20 done: {head['ms_per_step']:.3f} ms/step", file=sys.stderr,
               flush=True)
     for name, fn in (("grid", bench_grid), ("batch", bench_batch), ("diff", bench_diff),
