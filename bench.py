@@ -498,17 +498,6 @@ def bench_diff(steps, cpu_leg=True):
     rp, c, w = sssp.to_device(g, "cuda")
     gd = torch.zeros(g.n, dtype=torch.float32, device="cuda")
     gd[torch.from_numpy(t).long().cuda()] = 1.0
-    # the forward's options come from the autotuner (this graph, five sources)
-    tuned = sssp.autotune(rp, c, w, s)
-    ev0 = HipEvents()
-    sd = sssp.Solver(rp, c, w, validate=False, want_pred=False, no_autotune=True)
-    sd(s)
-    dms = []
-    for _ in range(max(1, steps)):
-        e = ev0.pair()
-        sd(s, events=e)
-        dms.append(ev0.ms(e))
-    del sd
     solver = sssp.Solver(rp, c, w, validate=False, want_pred=False)
     solver(s)
     ev = HipEvents()
@@ -544,7 +533,6 @@ def bench_diff(steps, cpu_leg=True):
     bf, reached, m_r = solve_bytes_from_dist(g, dist)
     out = {"workload": "rmat22_f32_1024_targets", "n": g.n, "m": g.m, "m_cc": mcc,
            "forward_ms": fwd_ms, "backward_ms": bwd_ms, "backward_status": status,
-           "autotune": {"tuned_options": tuned, "forward_ms_default_options": float(np.mean(dms))},
            "forward_gteps": mcc / (fwd_ms * 1e-3) / 1e9,
            "roofline_forward": roofline("k_solve", bf, fwd_ms, workload="rmat22f32"),
            "roofline_backward": roofline("k_bwd", b_bwd(g.n, g.m, reached), bwd_ms,

@@ -155,14 +155,6 @@ typedef struct {
                               else 1), < 0 = unbounded (fully
                               asynchronous partitions).  Batched solves are
                               always unbounded.  Results never depend on it. */
-  int32_t heavy_degree;    /* rows of at least this many arcs are expanded only
-                              while their distance lies in the sub-bucket of
-                              width delta / 8 that holds their partition's least
-                              pending distance (hubs' distances drop several
-                              times while a wide bucket is settled; each drop
-                              re-expands every arc); 0 = auto (the autotune
-                              cache, else none), < 0 = none.  Scheduling only:
-                              results never depend on it. */
   void *event_start;       /* optional hipEvent_t recorded right before the
                               main kernel of the call (NULL = none)        */
   void *event_stop;        /* optional hipEvent_t recorded right after it  */

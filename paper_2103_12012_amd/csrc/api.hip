@@ -138,8 +138,7 @@ SolvePlan make_plan(const sssp_csr &g, const sssp_opts &o) {
   sssp_opts tuned;
   bool have = false;
   if (!(o.flags & SSSP_F_NO_AUTOTUNE) &&
-      (o.delta == 0 || o.num_partitions == 0 || o.wg_size == 0 || o.lag == 0 ||
-       o.heavy_degree == 0))
+      (o.delta == 0 || o.num_partitions == 0 || o.wg_size == 0 || o.lag == 0))
     have = autotune_lookup(g, &tuned);
   const double delta = o.delta != 0 ? o.delta : (have ? tuned.delta : 0.0);
   int P = o.num_partitions > 0 ? o.num_partitions
@@ -165,8 +164,6 @@ SolvePlan make_plan(const sssp_csr &g, const sssp_opts &o) {
   pl.grid = o.num_workgroups ? o.num_workgroups
                              : (have && tuned.num_workgroups ? tuned.num_workgroups : 0);
   pl.lag = o.lag ? o.lag : (have ? tuned.lag : 0);
-  pl.heavy_deg = o.heavy_degree > 0 ? o.heavy_degree
-                                    : (o.heavy_degree == 0 && have ? tuned.heavy_degree : 0);
   return pl;
 }
 
@@ -360,7 +357,6 @@ extern "C" int sssp_solve(const sssp_csr *g, int32_t source, const sssp_opts *o,
   d.bsize = pl.bsize;
   d.unit0 = 0;
   d.nwords = (g->n + 31) / 32;
-  d.heavy_deg = pl.heavy_deg;
   opts.lag = pl.lag;
   return run_solves(descs, L, pl.nparts, g->wtype, pl.bs,
                     plan_grid(g->wtype, pl.bs, pl.grid, pl.grid_per_cu, solve_mode(opts.flags)),
@@ -394,7 +390,6 @@ extern "C" int sssp_solve_batch(int32_t num_graphs, const sssp_csr *graphs, int3
       if (opts.num_partitions == 0) opts.num_partitions = tuned.num_partitions;
       if (opts.wg_size == 0) opts.wg_size = tuned.wg_size;
       if (opts.num_workgroups == 0) opts.num_workgroups = tuned.num_workgroups;
-      if (opts.heavy_degree == 0) opts.heavy_degree = tuned.heavy_degree;
     }
     opts.flags |= SSSP_F_NO_AUTOTUNE;
   }
@@ -447,7 +442,6 @@ extern "C" int sssp_solve_batch(int32_t num_graphs, const sssp_csr *graphs, int3
     d.bsize = pl.bsize;
     d.unit0 = unit0;
     d.nwords = (g.n + 31) / 32;
-    d.heavy_deg = pl.heavy_deg;
     unit0 += pl.nparts;
     bs = bs > pl.bs ? bs : pl.bs;
     grid = grid > pl.grid ? grid : pl.grid;

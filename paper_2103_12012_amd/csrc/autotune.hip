@@ -5,8 +5,7 @@
 // unbounded bucket; then P around its default; then lag; then the workgroup
 // size; then the grid size).  Each setting is timed from five sources and
 // scored by the median time; a setting replaces the best so far only when
-// its median is more than 3% faster and it is not slower from the caller's
-// own source.
+// it is more than 3% faster.
 //
 // The bucket width trades the two effects the paper's related-work section
 // describes for delta-stepping: a wide bucket exposes more parallel work per
@@ -82,8 +81,7 @@ void load_json(const char *path) {
   while ((k = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, k);
   std::fclose(f);
   // one entry per line: {"key": "...", "delta": D, "num_partitions": P,
-  //                      "wg_size": W, "num_workgroups": G, "lag": L,
-  //                      "heavy_degree": H} (H may be absent: 0)
+  //                      "wg_size": W, "num_workgroups": G, "lag": L}
   size_t pos = 0;
   while ((pos = text.find("{\"key\": \"", pos)) != std::string::npos) {
     const size_t ks = pos + 9;
@@ -91,11 +89,11 @@ void load_json(const char *path) {
     if (ke == std::string::npos) break;
     const std::string key = text.substr(ks, ke - ks);
     double delta = 0;
-    int P = 0, W = 0, G = 0, Lg = 0, H = 0;
+    int P = 0, W = 0, G = 0, Lg = 0;
     if (std::sscanf(text.c_str() + ke + 1,
                     ", \"delta\": %lf, \"num_partitions\": %d, \"wg_size\": %d, "
-                    "\"num_workgroups\": %d, \"lag\": %d, \"heavy_degree\": %d",
-                    &delta, &P, &W, &G, &Lg, &H) >= 5) {
+                    "\"num_workgroups\": %d, \"lag\": %d",
+                    &delta, &P, &W, &G, &Lg) == 5) {
       sssp_opts o;
       std::memset(&o, 0, sizeof(o));
       o.delta = delta;
@@ -103,7 +101,6 @@ void load_json(const char *path) {
       o.wg_size = W;
       o.num_workgroups = G;
       o.lag = Lg;
-      o.heavy_degree = H;
       g_cache[key] = o;
     }
     pos = ke;
@@ -119,9 +116,9 @@ void save_json(const char *path) {
     const sssp_opts &o = kv.second;
     std::fprintf(f,
                  "{\"key\": \"%s\", \"delta\": %.17g, \"num_partitions\": %d, \"wg_size\": %d, "
-                 "\"num_workgroups\": %d, \"lag\": %d, \"heavy_degree\": %d}%s\n",
+                 "\"num_workgroups\": %d, \"lag\": %d}%s\n",
                  kv.first.c_str(), o.delta, o.num_partitions, o.wg_size, o.num_workgroups,
-                 o.lag, o.heavy_degree, ++i < g_cache.size() ? "," : "");
+                 o.lag, ++i < g_cache.size() ? "," : "");
   }
   std::fprintf(f, "]\n");
   std::fclose(f);
@@ -280,10 +277,9 @@ extern "C" int sssp_autotune(const sssp_csr *g, int32_t source, void *dist_scrat
     std::vector<float> sorted = per;
     std::sort(sorted.begin(), sorted.end());
     const float score = sorted[ns / 2];
-    // a new setting must win the median by more than run-to-run noise (3%)
-    // and must not be slower from the caller's own source: the defaults,
-    // tried first, stay unless something is clearly faster
-    if (!found || (score < 0.97f * best_score && per[0] <= best_per[0])) {
+    // a new setting must win by more than run-to-run noise (3%): the
+    // defaults, tried first, stay unless something is clearly faster
+    if (!found || score < 0.97f * best_score) {
       best_score = score;
       best_per = per;
       cur = cand;
@@ -298,14 +294,6 @@ extern "C" int sssp_autotune(const sssp_csr *g, int32_t source, void *dist_scrat
     for (double f : {0.25, 0.5, 1.0, 2.0, 4.0, 8.0, 16.0, 32.0, 64.0, -1.0}) {
       sssp_opts c = base;
       c.delta = f < 0 ? -1.0 : mean_w * f;
-      if ((rc = trial(c))) return rc;
-    }
-  }
-  if (fixed.heavy_degree == 0 && cur.delta >= 0) {  // the heavy-row rule needs a finite width
-    const sssp_opts base = cur;
-    for (int h : {256, 64}) {
-      sssp_opts c = base;
-      c.heavy_degree = h;
       if ((rc = trial(c))) return rc;
     }
   }
@@ -459,17 +447,9 @@ extern "C" int sssp_autotune_batch(int32_t num_graphs, const sssp_csr *graphs, i
   if ((rc = trial(cur))) return rc;
   if (fixed.delta == 0) {
     const sssp_opts base = cur;
-    for (double f : {0.25, 0.5, 1.0, 2.0, 4.0, 8.0, 16.0, -1.0}) {
+    for (double f : {0.25, 0.5, 1.0, 2.0, 4.0}) {
       sssp_opts c = base;
-      c.delta = f < 0 ? -1.0 : mean_w * f;
-      if ((rc = trial(c))) return rc;
-    }
-  }
-  if (fixed.heavy_degree == 0 && cur.delta >= 0) {
-    const sssp_opts base = cur;
-    for (int h : {256, 64}) {
-      sssp_opts c = base;
-      c.heavy_degree = h;
+      c.delta = mean_w * f;
       if ((rc = trial(c))) return rc;
     }
   }

@@ -197,8 +197,6 @@ struct SolveDesc {
   int32_t unit0;               // first scheduling unit (partition) index
   int32_t nwords;              // ceil(n/32)
   float auto_factor;           // DELTA_AUTO: width = factor * mean sampled cost
-  int32_t heavy_deg;           // rows of at least this many arcs settle in delta/8
-                               // sub-buckets (0 = no such rule)
 };
 
 // Device-wide control block living in the workspace.  The pending-work

@@ -17,7 +17,6 @@ struct SolvePlan {
   unsigned long long delta = DELTA_INF;  // DELTA_AUTO: set on the device
   float auto_factor = 0.0f;              // for DELTA_AUTO
   int lag = 0;                           // window in buckets (0 = default)
-  int heavy_deg = 0;                     // heavy-row threshold (0 = none)
 };
 
 DevInfo device_info();

@@ -209,11 +209,6 @@ template <> struct Dist<SSSP_W_U32> {
     if (delta == DELTA_INF) return DELTA_INF;
     return (d / delta + 1) * delta;
   }
-  // delta / 2^k (at least 1)
-  __device__ static __forceinline__ unsigned long long narrow(unsigned long long delta, int k) {
-    if (delta == DELTA_INF) return DELTA_INF;
-    return (delta >> k) > 0 ? (delta >> k) : 1ull;
-  }
 };
 template <> struct Dist<SSSP_W_F32> {
   static constexpr uint32_t INF_BITS = 0x7F800000u;
@@ -244,12 +239,6 @@ template <> struct Dist<SSSP_W_F32> {
     unsigned long long tb = __float_as_uint(tf);
     if (tb <= d) tb = d + 1;
     return tb;
-  }
-  // delta / 2^k (at least the smallest normal)
-  __device__ static __forceinline__ unsigned long long narrow(unsigned long long delta, int k) {
-    if (delta == DELTA_INF) return DELTA_INF;
-    const float f = __uint_as_float((uint32_t)delta) * __uint_as_float((uint32_t)(127 - k) << 23);
-    return f >= 1.17549435e-38f ? __float_as_uint(f) : 0x00800000u;
   }
 };
 
@@ -860,23 +849,9 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
 #pragma unroll
     for (int k = 1; k < NW; k++) umin = s_red[k] < umin ? s_red[k] : umin;
     unsigned long long T = 0;  // end of the bucket being settled (bucket modes)
-    // Rows of at least heavy_deg arcs (0 = no such rule) are expanded only
-    // while their distance lies below Th, the end of the sub-bucket of width
-    // delta / 8 that holds the unit's least pending distance; a heavy row
-    // above it goes back to the inbox.  A hub has many in-arcs, so its
-    // tentative distance tends to drop several times while its bucket is
-    // settled, and every drop would re-expand all of its arcs; narrowing
-    // its bucket expands it closer to its final distance.  The vertex that
-    // holds the unit's least distance is always expanded (it lies below
-    // Th), so every batch makes progress.
-    const int heavy_deg = uni(s_desc.heavy_deg);
-    unsigned long long Th = 0;
-    unsigned int hdefer = 0;
-    unsigned long long hmin = ~0ull;
     int cnt = 0;               // its claimed vertices
     if constexpr (!HEAP) {
       T = Dist<WT>::bucket_end(umin, delta);
-      if (heavy_deg > 0) Th = Dist<WT>::bucket_end(umin, Dist<WT>::narrow(delta, 3));
       // the lowest bucket is the frontier (with the distances just loaded);
       // the rest goes back to the inbox, one atomic or per word
       unsigned long long far = ~0ull;
@@ -1186,28 +1161,8 @@ __global__ __launch_bounds__(BS, BS == 1024 ? 4 : SSSP_SOLVE_MIN_WAVES) void k_s
               s_d[k] = (uint32_t)(lab[j] >> 32);
               s_rs[k] = r0;
               s_off[k] = r1 - r0;
-              if (heavy_deg > 0 && r1 - r0 >= heavy_deg && (lab[j] >> 32) >= Th) {
-                // a heavy row above the unit's heavy sub-bucket waits in the
-                // inbox: its distance is likely to drop again first
-                s_off[k] = 0;
-                const int u = s_v[k];
-                const uint32_t bit = 1u << (u & 31);
-                if (!(aor(&dirty[u >> 5], bit) & bit)) hdefer++;
-                const unsigned long long dk = lab[j] >> 32;
-                hmin = dk < hmin ? dk : hmin;
-              }
             }
           }
-        }
-        if (heavy_deg > 0) {
-          hdefer = wave_sum(hdefer);
-          hmin = wave_min(hmin);
-          if (lane == 0) {
-            if (hdefer) atomicAdd(&s_new, hdefer);
-            if (hmin != ~0ull) atomicMin(&s_far, hmin);
-          }
-          hdefer = 0;
-          hmin = ~0ull;
         }
         __syncthreads();
         int degs[EPT];

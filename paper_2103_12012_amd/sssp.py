@@ -52,8 +52,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_double), ("num_partitions", ctypes.c_int32),
                 ("wg_size", ctypes.c_int32), ("num_workgroups", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("lag", ctypes.c_int32), ("heavy_degree", ctypes.c_int32),
-                ("event_start", ctypes.c_void_p),
+                ("lag", ctypes.c_int32), ("event_start", ctypes.c_void_p),
                 ("event_stop", ctypes.c_void_p), ("keep_out", ctypes.c_void_p)]
 
 
@@ -154,8 +153,7 @@ def _csr(row_ptr, col, w) -> CSR:
 
 def make_opts(delta=0.0, num_partitions=0, wg_size=0, num_workgroups=0, max_rounds=0,
               validate=True, sync=False, local=False, no_autotune=False, events=None,
-              lag=0, buffer_cross=False, local_heap=False, idle_prune=False,
-              heavy_degree=0) -> Opts:
+              lag=0, buffer_cross=False, local_heap=False, idle_prune=False) -> Opts:
     flags = (F_VALIDATE if validate else 0) | (F_SYNC if sync else 0) | \
             (F_PRUNE_LOCAL if local else 0) | (F_NO_AUTOTUNE if no_autotune else 0) | \
             (F_BUFFER_CROSS if buffer_cross else 0) | (F_LOCAL_HEAP if local_heap else 0) | \
@@ -168,7 +166,6 @@ def make_opts(delta=0.0, num_partitions=0, wg_size=0, num_workgroups=0, max_roun
     o.max_rounds = int(max_rounds)
     o.flags = flags
     o.lag = int(lag)
-    o.heavy_degree = int(heavy_degree)
     if events is not None:
         o.event_start, o.event_stop = events
     return o
@@ -242,13 +239,13 @@ class Solver:
     def __init__(self, row_ptr, col, w, *, delta=0.0, num_partitions=0, wg_size=0,
                  num_workgroups=0, max_rounds=0, validate=True, want_pred=True,
                  stats=False, lag=0, no_autotune=False, buffer_cross=False,
-                 local_heap=False, idle_prune=False, want_keep=False, heavy_degree=0):
+                 local_heap=False, idle_prune=False, want_keep=False):
         self.g = _csr(row_ptr, col, w)
         self._keep = (row_ptr, col, w)
         self.opts = make_opts(delta, num_partitions, wg_size, num_workgroups, max_rounds,
                               validate=validate, lag=lag, no_autotune=no_autotune,
                               buffer_cross=buffer_cross, local_heap=local_heap,
-                              idle_prune=idle_prune, heavy_degree=heavy_degree)
+                              idle_prune=idle_prune)
         # idle pruning: the keep flags of the arcs (1 kept, 0 deleted during the solve)
         self.keep = None
         if idle_prune and want_keep:
@@ -304,7 +301,7 @@ class BatchSolver:
 
     def __init__(self, graphs, solve_graph, solve_source, *, delta=0.0, num_partitions=0,
                  wg_size=0, num_workgroups=0, validate=False, want_pred=True, stats=False,
-                 buffer_cross=False, local_heap=False, idle_prune=False, heavy_degree=0):
+                 buffer_cross=False, local_heap=False, idle_prune=False):
         self._keep = graphs
         self.gs = (CSR * len(graphs))(*[_csr(*g) for g in graphs])
         wdt = graphs[0][2].dtype
@@ -320,8 +317,7 @@ class BatchSolver:
         self.total = tot
         self.opts = make_opts(delta, num_partitions, wg_size, num_workgroups,
                               validate=validate, buffer_cross=buffer_cross,
-                              local_heap=local_heap, idle_prune=idle_prune,
-                              heavy_degree=heavy_degree)
+                              local_heap=local_heap, idle_prune=idle_prune)
         self.dist = torch.empty(tot, dtype=wdt, device=dev)
         self.pred = torch.empty(tot, dtype=torch.int32, device=dev) if want_pred else None
         self.pred_edge = torch.empty(tot, dtype=torch.int32, device=dev)
@@ -368,8 +364,7 @@ class BatchSolver:
         self.ws = _workspace(lambda q: L.sssp_solve_batch(
             *args, ctypes.byref(self.opts), None, None, None, None, None, q, None), dev)
         return {"delta": best.delta, "num_partitions": best.num_partitions,
-                "wg_size": best.wg_size, "num_workgroups": best.num_workgroups,
-                "heavy_degree": best.heavy_degree}
+                "wg_size": best.wg_size, "num_workgroups": best.num_workgroups}
 
     def split(self, t):
         """Per-solve views of a batched output tensor."""
@@ -460,8 +455,7 @@ def autotune(row_ptr, col, w, source: int, cache_path: str | None = None, **fixe
                          _ptr(ws), ctypes.byref(nb), _stream())
     _check(rc, "sssp_autotune")
     return {"delta": best.delta, "num_partitions": best.num_partitions,
-            "wg_size": best.wg_size, "num_workgroups": best.num_workgroups, "lag": best.lag,
-            "heavy_degree": best.heavy_degree}
+            "wg_size": best.wg_size, "num_workgroups": best.num_workgroups, "lag": best.lag}
 
 
 # ------------------------------------------------------------------ helpers

@@ -52,7 +52,7 @@ def test_opts_init(lib):
 
 def test_struct_sizes():
     assert ctypes.sizeof(sssp.CSR) == 40
-    assert ctypes.sizeof(sssp.Opts) == 64
+    assert ctypes.sizeof(sssp.Opts) == 56
     assert ctypes.sizeof(sssp.Stats) == 120
 
 

@@ -1,7 +1,7 @@
 """GPU parity of the solve's optional modes against the oracle, through the
-C ABI: buffered cross-partition updates (SSSP_F_BUFFER_CROSS), the
+C ABI: buffered cross-partition updates (SSSP_F_BUFFER_CROSS) and the
 literal local rule of Alg. 3, one vertex at a time from an LDS binary heap
-(SSSP_F_LOCAL_HEAP), and the heavy-row scheduling rule (heavy_degree).  Every mode must give the oracle's distances,
+(SSSP_F_LOCAL_HEAP).  Every mode must give the oracle's distances,
 predecessors and predecessor arcs bit for bit, whatever delta, partition
 count, workgroup shape or schedule."""
 import numpy as np
@@ -17,8 +17,6 @@ pytestmark = pytest.mark.gpu
 MODES = {
     "buffered": dict(buffer_cross=True),
     "heap": dict(local_heap=True),
-    # scheduling rule, not a mode: rows of >= 64 arcs settle in delta/8 sub-buckets
-    "heavy64": dict(heavy_degree=64),
 }
 
 
@@ -132,7 +130,7 @@ def test_rmat20_full_size_pruned(mode):
     assert_solve_parity(g, s, (dist, pred.cpu().numpy(), pe_orig))
 
 
-@pytest.mark.parametrize("mode", ["buffered", "heavy64"])
+@pytest.mark.parametrize("mode", ["buffered"])
 def test_grid4096_full_size(mode):
     g = gen.grid(4096, 4096, seed=3)
     dist, pred, pe = gpu_solve(g, 0, **MODES[mode])
@@ -257,35 +255,3 @@ def test_idle_prune_refused_with_other_modes_and_batches():
     with pytest.raises(S.SSSPError) as ei:
         S.solve_batch([dev(g)], [0], [0], idle_prune=True)
     assert ei.value.code == -1
-
-
-@pytest.mark.parametrize("delta", [1, 100, 400, -1])
-@pytest.mark.parametrize("P", [1, 4, 256])
-def test_heavy_rule_every_row(c1, delta, P):
-    """heavy_degree = 1: every row waits unless it lies in the narrow
-    sub-bucket of its partition's least distance (the put-back path taken
-    for most vertices); exact at every delta and partition count, also for
-    batches and fp32."""
-    g, d, ref = c1
-    assert_solve_parity(g, 0, gpu_solve(g, 0, d=d, num_partitions=P, delta=delta,
-                                        heavy_degree=1), ref)
-
-
-def test_heavy_rule_fp32_and_batch():
-    g = gen.rmat(14, 22, weight="f32", wlo=0.5, whi=1.5)
-    s = int(gen.random_sources(g, 1, 5)[0])
-    for h in (1, 64):
-        assert_solve_parity(g, s, gpu_solve(g, s, heavy_degree=h))
-    rng = np.random.default_rng(13)
-    graphs = [gen.rmat(int(sc), 6100 + i) for i, sc in enumerate(rng.integers(8, 14, size=6))]
-    sg, ss = [], []
-    for i, gi in enumerate(graphs):
-        for src in gen.random_sources(gi, 2, 8100 + i):
-            sg.append(i)
-            ss.append(int(src))
-    S = sssp_mod()
-    dists, preds, pes = S.solve_batch([dev(x) for x in graphs], sg, ss, heavy_degree=16,
-                                      delta=500.0)
-    for k, (gi, src) in enumerate(zip(sg, ss)):
-        assert_solve_parity(graphs[gi], src, (dists[k].cpu().numpy().view(np.uint32),
-                                              preds[k].cpu().numpy(), pes[k].cpu().numpy()))
