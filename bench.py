@@ -273,6 +273,7 @@ def bench_rmat20(steps, warmup, cpu_leg=True, tune=True):
         "roofline_solve": roofline("k_solve", b_solve, solve_ms, workload="rmat20"),
         "roofline_prune": rp_prune,
         "prune_stats": {"edges_pruned": prune_stats["edges_pruned"],
+                        "hub_pass_deleted": prune_stats["hub_pruned"],
                         "entries_examined": prune_stats["wedges"]},
         "autotune": autotune_res,
     }

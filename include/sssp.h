@@ -124,7 +124,12 @@ enum {
      opts->keep_out, if set, receives the keep flags; stats->edges_pruned and
      stats->wedges count deleted arcs and two-arc paths examined.  Not
      together with the two modes above (SSSP_ERR_ARG). */
-  SSSP_F_IDLE_PRUNE = 1u << 6
+  SSSP_F_IDLE_PRUNE = 1u << 6,
+  /* sssp_prune: skip the hub pass (the arcs are tested through the
+     HUB_K = 64 vertices with the most two-arc paths first, with integer
+     costs, GLOBAL scope and n <= 2^23); the result is the same, only the
+     time changes.  For comparisons. */
+  SSSP_F_PRUNE_NO_HUBS = 1u << 7
 };
 
 typedef struct {
@@ -179,8 +184,11 @@ typedef struct {
   uint64_t vertices_expanded;/* frontier vertices processed (with repeats) */
   uint64_t batches;          /* frontier batches (bucket rounds)          */
   uint64_t edges_pruned;     /* sssp_prune: arcs deleted                   */
-  uint64_t wedges;           /* sssp_prune: two-arc paths examined         */
-  uint64_t reserved[6];
+  uint64_t wedges;           /* sssp_prune: list entries examined by the
+                                scans (candidate two-arc paths)           */
+  uint64_t hub_pruned;       /* sssp_prune: arcs deleted by the hub pass
+                                (included in edges_pruned)                */
+  uint64_t reserved[5];
 } sssp_stats;
 
 /* --------------------------------------------------------------- prune */

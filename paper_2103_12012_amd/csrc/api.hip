@@ -482,7 +482,8 @@ extern "C" int sssp_prune(const sssp_csr *g, const sssp_opts *o, uint8_t *keep,
   const int bsize = (g->n + P - 1) / P;
   const int local = (opts.flags & SSSP_F_PRUNE_LOCAL) ? 1 : 0;
   int32_t *dev_status = nullptr;
-  rc = launch_prune(*g, local, bsize, keep, out_row_ptr, out_col, out_w, edge_map, stats,
+  const bool hubs = !(opts.flags & SSSP_F_PRUNE_NO_HUBS);
+  rc = launch_prune(*g, local, hubs, bsize, keep, out_row_ptr, out_col, out_w, edge_map, stats,
                     static_cast<char *>(ws), device_info().cus,
                     (opts.flags & SSSP_F_VALIDATE) != 0, opts.event_start, opts.event_stop,
                     &dev_status, st);

@@ -30,7 +30,8 @@ hipError_t launch_scan_sums(int32_t *tile_sum, int ntiles, int32_t *total, hipSt
 
 // prune.hip
 size_t prune_ws_bytes(int n, int m, bool compact);
-int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t *out_row_ptr,
+int launch_prune(const sssp_csr &g, int local, bool hubs, int bsize, uint8_t *keep,
+                 int32_t *out_row_ptr,
                  int32_t *out_col, void *out_w, int32_t *edge_map, sssp_stats *stats,
                  char *ws, int grid_cus, bool validate, void *ev_start, void *ev_stop,
                  int32_t **status_out, hipStream_t st);

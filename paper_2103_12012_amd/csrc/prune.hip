@@ -77,10 +77,24 @@ constexpr int HV_TARGET_BIG = 1 << 20;  // big tier: larger items, fewer table r
 constexpr int SORT_MIN = 16;         // lists of SORT_MIN+1 .. SORT_MAX entries
 constexpr int SORT_MAX = 4096;       //   are sorted by cost
 constexpr int SORT_WAVE = 4 * 64;    // longest list sorted by one wave
-constexpr int Q_D0 = 16;             // first scan chunk of an arc
+#ifndef SSSP_Q_D0
+#define SSSP_Q_D0 16
+#endif
+constexpr int Q_D0 = SSSP_Q_D0;      // first scan chunk of an arc
 constexpr int Q_DMAX = 1024;         // chunk cap
 constexpr int G_UNIT = 64;           // global table sizes are multiples of this
 constexpr uint32_t VAL_INF = 0xFFFFFFFFu;
+// Hub pass: the HUB_K vertices with the most two-arc paths through them
+// (the largest min(in-degree, out-degree)) are tried as middles of every
+// arc before the scans, from dense per-vertex rows of 8-bit cost codes; an
+// arc they delete is not scanned.  Only for integer costs, GLOBAL scope and
+// n <= HUB_NMAX (the two code tables take 2 * HUB_K bytes per vertex).
+constexpr int HUB_K = 32;
+constexpr int HUB_NMAX = 1 << 23;
+constexpr int HUB_BINS = 512;         // score histogram: 16 bins per octave
+constexpr uint8_t HUB_NONE = 0xFF;    // no hub / no arc
+// parameters after the histogram and the hub ids
+constexpr int HP_WMIN = 0, HP_WMAX = 1, HP_CNT = 2, HP_CNT_TB = 3, HP_STEP = 4, HP_N = 8;
 
 template <int WT> struct Tri;
 template <> struct Tri<SSSP_W_U32> {
@@ -138,6 +152,12 @@ struct TbArgs {
   int32_t *tickets; // TK_* counters
   int32_t *status;
   sssp_stats *stats;
+  // hub pass (hubs != 0): the HUB_K best middles tried for every scanned arc first
+  int hubs;
+  uint8_t *hin;     // n x HUB_K: code of the cheapest arc v -> hub k (HUB_NONE = none)
+  uint8_t *hout;    // n x HUB_K: code of the cheapest arc hub k -> v
+  int32_t *hubm;    // HUB_BINS histogram, HUB_K hub ids, then HP_* parameters
+                    // (HP_WMIN / HP_WMAX: least and greatest cost)
 };
 
 __device__ __forceinline__ uint32_t tb_hash(int y, int bits) {
@@ -226,6 +246,15 @@ __global__ void k_tb_zero(TbArgs a) {
     a.bfill[i] = 0;
   }
   for (int i = t; i < 2 * a.n; i += stride) a.work[i] = 0;
+  if (a.hubs) {
+    for (int i = t; i < HUB_BINS; i += stride) a.hubm[i] = 0;
+    if (t == 0) {
+      a.hubm[HUB_BINS + HUB_K + HP_WMIN] = -1;  // 0xFFFFFFFF as uint32
+      a.hubm[HUB_BINS + HUB_K + HP_WMAX] = 0;
+      a.hubm[HUB_BINS + HUB_K + HP_CNT] = 0;
+      a.hubm[HUB_BINS + HUB_K + HP_CNT_TB] = 0;
+    }
+  }
 }
 
 // Tail of every arc, in tiles of TL_E arcs: k_tb_tilerow records the row
@@ -274,6 +303,217 @@ __global__ __launch_bounds__(TL_BS) void k_tb_tails(TbArgs a) {
     }
     __syncthreads();
   }
+}
+
+// ------------------------------------------------------------------ hubs
+// Hub pass.  Most deleted arcs have a witness through one of a few
+// high-degree middles (on R-MAT 20, 66% of them through the 64 vertices
+// with the most two-arc paths), which a scan reaches only after the
+// cheaper entries of its list.  So every arc about to be scanned first
+// tries those HUB_K middles at once: row u of `hin` holds the code of the
+// cheapest arc u -> hub k, row x of `hout` the code of the cheapest arc
+// hub k -> x (HUB_NONE when there is none, and always for a hub's own
+// entry in its own rows, since the middle must differ from u and x), and
+// the arc is deleted, and not scanned, when some k has both arcs with a
+// sum below W.  Codes are upper bounds of the costs, lo + code * step >=
+// cost (exact when the costs span at most 254), so every arc deleted this
+// way is in the deletion set; any other arc is scanned as before, and the
+// result is the same.
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T x) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const T y = __shfl_xor(x, o, WAVE);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint32_t *hub_params(const TbArgs &a) {
+  return reinterpret_cast<uint32_t *>(a.hubm + HUB_BINS + HUB_K);
+}
+
+// Score of v as a middle (its two-arc paths are at least score^2; 0 = it
+// cannot be one) and its histogram bin (16 bins per octave, monotone).
+__device__ __forceinline__ int hub_score(const TbArgs &a, int v) {
+  const int od = a.row_ptr[v + 1] - a.row_ptr[v], id = a.ccnt[v];
+  return od < id ? od : id;
+}
+__device__ __forceinline__ int hub_bin(int s) {
+  return (int)((__float_as_uint((float)s) - 0x3F800000u) >> 19);
+}
+
+// Pass 1: score histogram.  Lanes of a wave with equal bins add once.
+__global__ __launch_bounds__(256) void k_hub_hist(TbArgs a) {
+  __shared__ int s_h[HUB_BINS];
+  if (*a.status) return;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < HUB_BINS; i += 256) s_h[i] = 0;
+  __syncthreads();
+  const int t = blockIdx.x * 256 + tid;
+  const int stride = gridDim.x * 256;
+  const int nr = (a.n + WAVE - 1) / WAVE * WAVE;  // whole waves stay in the loop
+  for (int v = t; v < nr; v += stride) {
+    int b = -1;
+    if (v < a.n) {
+      const int sc = hub_score(a, v);
+      if (sc > 0) b = hub_bin(sc);
+    }
+    // one add per distinct bin of the wave
+    unsigned long long left = __ballot(b >= 0);
+    while (left) {
+      const int lead = __ffsll((long long)left) - 1;
+      const int bl = __shfl(b, lead, WAVE);
+      const unsigned long long same = __ballot(b == bl) & left;
+      if (lane_id() == lead) atomicAdd(&s_h[bl], __popcll(same));
+      left &= ~same;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < HUB_BINS; i += 256)
+    if (s_h[i]) atomicAdd(&a.hubm[i], s_h[i]);
+}
+
+// Pass 2: the hub list; every vertex's two code rows start empty.  Each
+// workgroup first finds the threshold bin (every vertex above it is a hub,
+// and the first `need` of its own) from the histogram.
+__global__ __launch_bounds__(256) void k_hub_take(TbArgs a) {
+  __shared__ int s_suf[HUB_BINS + 1];  // vertices in bins >= b
+  __shared__ int s_ws[256 / WAVE + 1];
+  __shared__ int s_tb, s_need;
+  if (*a.status) return;
+  uint32_t *hp = hub_params(a);
+  {
+    // suffix sums of the histogram: two bins per thread, reversed scan
+    constexpr int PER = HUB_BINS / 256;
+    static_assert(HUB_BINS % 256 == 0, "bins per thread");
+    int c[PER], sum = 0;
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+      c[j] = a.hubm[HUB_BINS - 1 - (threadIdx.x * PER + j)];
+      sum += c[j];
+    }
+    int tot;
+    int run = block_excl_scan1<256>(sum, s_ws, &tot);
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+      run += c[j];
+      s_suf[HUB_BINS - 1 - (threadIdx.x * PER + j)] = run;
+    }
+    if (threadIdx.x == 0) {
+      s_suf[HUB_BINS] = 0;
+      s_tb = -1;
+      s_need = 0;
+    }
+    __syncthreads();
+    // the highest bin b whose suffix reaches HUB_K (unique: suffixes only
+    // grow as b falls)
+    for (int b = threadIdx.x; b < HUB_BINS; b += 256)
+      if (s_suf[b] >= HUB_K && s_suf[b + 1] < HUB_K) {
+        s_tb = b;
+        s_need = HUB_K - s_suf[b + 1];
+      }
+    __syncthreads();
+  }
+  const int tb = s_tb, need = s_need;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const uint32_t lo = hp[HP_WMIN], hi = hp[HP_WMAX];
+    const uint32_t span = hi >= lo ? hi - lo : 0u;
+    const uint32_t step = (uint32_t)(((unsigned long long)span + 253ull) / 254ull);
+    hp[HP_STEP] = step > 0u ? step : 1u;
+  }
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int stride = gridDim.x * 256;
+  const int4 none = make_int4(-1, -1, -1, -1);
+  for (int v = t; v < a.n; v += stride) {
+    const int sc = hub_score(a, v);
+    if (sc > 0) {
+      const int b = hub_bin(sc);
+      if (b > tb || (b == tb && (int)atomicAdd(&hp[HP_CNT_TB], 1u) < need)) {
+        const int idx = (int)atomicAdd(&hp[HP_CNT], 1u);  // at most HUB_K in all
+        if (idx < HUB_K) a.hubm[HUB_BINS + idx] = v;
+      }
+    }
+    int4 *ri = reinterpret_cast<int4 *>(a.hin + (size_t)v * HUB_K);
+    int4 *ro = reinterpret_cast<int4 *>(a.hout + (size_t)v * HUB_K);
+#pragma unroll
+    for (int k = 0; k < HUB_K / 16; k++) {
+      ri[k] = none;
+      ro[k] = none;
+    }
+  }
+}
+
+// Code of cost c: the least code whose value lo + code * step is >= c.
+__device__ __forceinline__ uint32_t hub_code(uint32_t c, uint32_t lo, uint32_t step) {
+  return (uint32_t)(((unsigned long long)(c - lo) + step - 1ull) / step);
+}
+
+// Pass 3 (blockIdx.y = hub k): the code rows from hub k's out-row (arcs
+// k -> x into hout) and in-column (arcs u -> k into hin); self-loops are
+// never a middle's arc.  Plain byte stores: where parallel arcs make two
+// stores to one byte, whichever lands is the code of one of those arcs,
+// still an upper bound of the cheapest (the row is sorted, so out-row runs
+// store the cheapest of the run).
+__global__ __launch_bounds__(256) void k_hub_tables(TbArgs a) {
+  if (*a.status) return;
+  const uint32_t *hp = hub_params(a);
+  const int k = blockIdx.y;
+  if (k >= (int)min(hp[HP_CNT], (uint32_t)HUB_K)) return;
+  const uint32_t lo = hp[HP_WMIN], step = hp[HP_STEP];
+  const int h = a.hubm[HUB_BINS + k];
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int stride = gridDim.x * 256;
+  const int r0 = a.row_ptr[h], r1 = a.row_ptr[h + 1];
+  for (int p = r0 + t; p < r1; p += stride) {
+    const int x = a.col[p];
+    if (x == h || (unsigned)x >= (unsigned)a.n || (p > r0 && a.col[p - 1] == x)) continue;
+    uint32_t c = a.w[p];
+    for (int q = p + 1; q < r1 && a.col[q] == x; q++) c = min(c, a.w[q]);  // a run of parallel arcs
+    a.hout[(size_t)x * HUB_K + k] = (uint8_t)hub_code(c, lo, step);
+  }
+  const int c0 = a.cb[h], c1 = a.cb[h + 1];
+  for (int p = c0 + t; p < c1; p += stride) {
+    const int2 uw = a.cyw[p];
+    if (uw.x != h && (unsigned)uw.x < (unsigned)a.n)
+      a.hin[(size_t)uw.x * HUB_K + k] = (uint8_t)hub_code((uint32_t)uw.y, lo, step);
+  }
+}
+
+// Least code sum over the byte lanes of two words (an absent code, 255,
+// makes a sum of at least 255, which never passes the test below).
+__device__ __forceinline__ uint32_t min_code_sum(uint32_t p, uint32_t q) {
+  const uint32_t s0 = (p & 0x00FF00FFu) + (q & 0x00FF00FFu);
+  const uint32_t s1 = ((p >> 8) & 0x00FF00FFu) + ((q >> 8) & 0x00FF00FFu);
+  const uint32_t a0 = s0 & 0xFFFFu, a1 = s0 >> 16, b0 = s1 & 0xFFFFu, b1 = s1 >> 16;
+  const uint32_t m0 = a0 < a1 ? a0 : a1, m1 = b0 < b1 ? b0 : b1;
+  return m0 < m1 ? m0 : m1;
+}
+
+// Does some hub middle delete arc (u, x, W)?  (lo + c1 step) + (lo + c2
+// step) < W with c1 + c2 the least code sum.
+__device__ __forceinline__ bool hub_witness(const TbArgs &a, int u, int x, uint32_t W) {
+  const uint32_t *hp = hub_params(a);
+  const unsigned long long lo2 = 2ull * hp[HP_WMIN], step = hp[HP_STEP];
+  if ((unsigned long long)W <= lo2) return false;
+  const uint4 *ri = reinterpret_cast<const uint4 *>(a.hin + (size_t)u * HUB_K);
+  const uint4 *ro = reinterpret_cast<const uint4 *>(a.hout + (size_t)x * HUB_K);
+  uint4 p[HUB_K / 16], q[HUB_K / 16];
+#pragma unroll
+  for (int k = 0; k < HUB_K / 16; k++) {
+    p[k] = ri[k];
+    q[k] = ro[k];
+  }
+  uint32_t best = 0xFFFFu;
+#pragma unroll
+  for (int k = 0; k < HUB_K / 16; k++) {
+    best = min(best, min_code_sum(p[k].x, q[k].x));
+    best = min(best, min_code_sum(p[k].y, q[k].y));
+    best = min(best, min_code_sum(p[k].z, q[k].z));
+    best = min(best, min_code_sum(p[k].w, q[k].w));
+  }
+  return lo2 + (unsigned long long)best * step < (unsigned long long)W;
 }
 
 // ------------------------------------------------------------------ CSC
@@ -332,6 +572,7 @@ __global__ __launch_bounds__(C_BS) void k_csc_scatter(TbArgs a) {
   for (int b = threadIdx.x; b < a.nb; b += C_BS)
     if (s_h[b]) s_h[b] = a.bstart[b] + atomicAdd(&a.bfill[b], s_h[b]);
   __syncthreads();
+  uint32_t lo = 0xFFFFFFFFu, hi = 0u;  // cost range (for the hub pass's codes)
   for (int e = e0 + threadIdx.x; e < e1; e += C_U * C_BS) {
     int x[C_U], u[C_U], wv[C_U];
 #pragma unroll
@@ -349,7 +590,30 @@ __global__ __launch_bounds__(C_BS) void k_csc_scatter(TbArgs a) {
       if (ek < e1) {
         a.rs[ek] = make_int2(x[k], wv[k]);
         a.stage[atomicAdd(&s_h[x[k] >> a.cs], 1)] = make_int4(x[k], u[k], wv[k], ek);
+        lo = min(lo, (uint32_t)wv[k]);
+        hi = max(hi, (uint32_t)wv[k]);
       }
+    }
+  }
+  if (a.hubs) {  // one global atomic pair per workgroup
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    __syncthreads();  // s_h is free again
+    uint32_t *s_r = reinterpret_cast<uint32_t *>(s_h);
+    if (threadIdx.x == 0) {
+      s_r[0] = 0xFFFFFFFFu;
+      s_r[1] = 0u;
+    }
+    __syncthreads();
+    if (lane_id() == 0 && lo <= hi) {
+      atomicMin(&s_r[0], lo);
+      atomicMax(&s_r[1], hi);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_r[0] <= s_r[1]) {
+      uint32_t *hp = hub_params(a);
+      atomicMin(&hp[HP_WMIN], s_r[0]);
+      atomicMax(&hp[HP_WMAX], s_r[1]);
     }
   }
 }
@@ -488,16 +752,6 @@ __device__ __forceinline__ void ord_put(const TbArgs &a, const SortSeg &g, int p
     a.cyw[p] = yw;
     a.ceid[p] = pay;
   }
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_max(T x) {
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) {
-    const T y = __shfl_xor(x, o, WAVE);
-    x = y > x ? y : x;
-  }
-  return x;
 }
 
 // CLS_K lists per thread and pass: queue the lists to order.  A pass
@@ -877,6 +1131,7 @@ struct Query {
   int beg, len;
   uint32_t W, stop;  // stop: entries of higher cost end the scan
   int eid, other;
+  int hub;           // 1: deleted by a hub middle (not scanned)
 };
 
 // Stop bound of a scan of a list with metadata lm (its lmeta entry) for an
@@ -922,6 +1177,14 @@ __device__ __forceinline__ Query make_query(const TbArgs &a, const Owner &o, int
     q.eid = p;
     q.other = x;
     q.stop = scan_stop(lm, q.W, q.len);
+  }
+  // an arc this owner scans tries the hub middles first
+  q.hub = 0;
+  if (a.hubs && q.len > 0 &&
+      hub_witness(a, o.mode == 0 ? q.other : o.t, o.mode == 0 ? o.t : q.other, q.W)) {
+    a.keep[q.eid] = 0;
+    q.len = 0;
+    q.hub = 1;
   }
   return q;
 }
@@ -1082,7 +1345,7 @@ __global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
   const int tid = threadIdx.x;
   const HList &hl = a.hl[TIER];
   const int total = a.hc[NTIER + TIER];
-  unsigned long long probes = 0;
+  unsigned long long probes = 0, hubdel = 0;
   for (;;) {
     if (tid == 0) s_t = atomicAdd(&a.tickets[TIER], 1);
     __syncthreads();
@@ -1148,6 +1411,7 @@ __global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
         cur = q.beg;
         H.qlim[tid] = q.beg + q.len;
         H.qrec[tid] = make_int4(q.other, (int)q.stop, (int)q.W, q.eid);
+        hubdel += q.hub;
       }
       __syncthreads();
       for (int D = Q_D0;; D = min(2 * D, Q_DMAX)) {
@@ -1180,6 +1444,10 @@ __global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
     __syncthreads();
   }
   if (a.stats && tid == 0 && probes) stat_add(&a.stats->wedges, probes);
+  if (a.stats) {
+    hubdel = wave_sum(hubdel);
+    if (lane_id() == 0 && hubdel) stat_add(&a.stats->hub_pruned, hubdel);
+  }
 }
 
 // Light owners: one wave per owner of llist, a private LDS table.
@@ -1191,7 +1459,7 @@ __global__ __launch_bounds__(LT_BS) void k_tb_light(TbArgs a) {
   TbLight &L = sw[threadIdx.x / WAVE];
   const int gw = (blockIdx.x * LT_BS + threadIdx.x) / WAVE;
   const int nw = gridDim.x * (LT_BS / WAVE);
-  unsigned long long probes = 0;
+  unsigned long long probes = 0, hubdel = 0;
   const int nlight = a.tickets[TK_LIGHT];
   for (int j = gw; j < nlight; j += nw) {
     {
@@ -1223,6 +1491,7 @@ __global__ __launch_bounds__(LT_BS) void k_tb_light(TbArgs a) {
           mycur = q.beg;
           L.qlim[lane] = q.beg + q.len;
           L.qrec[lane] = make_int4(q.other, (int)q.stop, (int)q.W, q.eid);
+          hubdel += q.hub;
         }
         wave_sync();
         for (int D = Q_D0;; D = min(2 * D, Q_DMAX)) {
@@ -1255,7 +1524,9 @@ __global__ __launch_bounds__(LT_BS) void k_tb_light(TbArgs a) {
   }
   if (a.stats) {
     probes = wave_sum(probes);
+    hubdel = wave_sum(hubdel);
     if (lane == 0 && probes) stat_add(&a.stats->wedges, probes);
+    if (lane == 0 && hubdel) stat_add(&a.stats->hub_pruned, hubdel);
   }
 }
 
@@ -1344,7 +1615,7 @@ namespace {
 struct PruneLayout {
   int cs, nb, ct, tiles;
   size_t src, trow, btot, bfill, bstart, stage, ccnt, cfill, cb, cyw, ceid, rs, lmeta, sl, llist, work, hflag, hl[NTIER][4], gsz,
-      goff, gkey, gval, tmp, misc, kbits, kpre, total;
+      goff, gkey, gval, tmp, misc, kbits, kpre, hin, hout, hubm, total;
 };
 
 PruneLayout prune_layout(int n, int m, bool compact) {
@@ -1400,6 +1671,13 @@ PruneLayout prune_layout(int n, int m, bool compact) {
   L.tmp = take(scan_tmp_bytes((int)(scan_n > (size_t)m + 1 ? scan_n : (size_t)m + 1)));
   L.misc = take(256);
   const size_t nw = ((size_t)m + 31) / 32;
+  if (n <= HUB_NMAX) {
+    L.hin = take((size_t)n * HUB_K);
+    L.hout = take((size_t)n * HUB_K);
+    L.hubm = take(4 * (HUB_BINS + HUB_K + HP_N));
+  } else {
+    L.hin = L.hout = L.hubm = 0;
+  }
   L.kbits = compact ? take(4 * nw) : 0;
   L.kpre = compact ? take(4 * (nw + 1)) : 0;
   L.total = off;
@@ -1492,7 +1770,8 @@ hipError_t launch_scan_kernels(const TbArgs &a, int grid_cus, hipStream_t st, Si
 
 size_t prune_ws_bytes(int n, int m, bool compact) { return prune_layout(n, m, compact).total; }
 
-int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t *out_row_ptr,
+int launch_prune(const sssp_csr &g, int local, bool hubs, int bsize, uint8_t *keep,
+                 int32_t *out_row_ptr,
                  int32_t *out_col, void *out_w, int32_t *edge_map, sssp_stats *stats,
                  char *ws, int grid_cus, bool validate, void *ev_start, void *ev_stop,
                  int32_t **status_out, hipStream_t st) {
@@ -1544,6 +1823,10 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   a.status = reinterpret_cast<int32_t *>(misc + 128);  // after 32 ticket counters
   a.hc = reinterpret_cast<int32_t *>(misc + 192);
   a.stats = stats;
+  a.hubs = hubs && !local && g.wtype == SSSP_W_U32 && n <= HUB_NMAX && m > 0;
+  a.hin = a.hubs ? reinterpret_cast<uint8_t *>(ws + L.hin) : nullptr;
+  a.hout = a.hubs ? reinterpret_cast<uint8_t *>(ws + L.hout) : nullptr;
+  a.hubm = a.hubs ? reinterpret_cast<int32_t *>(ws + L.hubm) : nullptr;
   uint32_t *kbits = out_row_ptr ? reinterpret_cast<uint32_t *>(ws + L.kbits) : nullptr;
   int32_t *kpre = out_row_ptr ? reinterpret_cast<int32_t *>(ws + L.kpre) : nullptr;
   *status_out = a.status;
@@ -1565,6 +1848,11 @@ int launch_prune(const sssp_csr &g, int local, int bsize, uint8_t *keep, int32_t
   }
   if (launch_excl_scan(a.ccnt, n, a.cb, tmp, st) != hipSuccess) return SSSP_ERR_HIP;
   if (m > 0) hipLaunchKernelGGL(k_csc_place, dim3(chunks), dim3(C_BS), 0, st, a);
+  if (a.hubs) {  // before the cost order, which moves the CSC entries
+    hipLaunchKernelGGL(k_hub_hist, dim3(grid_cus), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_hub_take, dim3(blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_hub_tables, dim3(64, HUB_K), dim3(256), 0, st, a);
+  }
   // Side streams, unless st is being captured (then everything stays on st).
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cap) != hipSuccess) return SSSP_ERR_HIP;

@@ -23,7 +23,7 @@ HEADER = os.path.join(_HERE, "..", "include", "sssp.h")
 
 W_U32, W_F32 = 0, 1
 F_VALIDATE, F_SYNC, F_PRUNE_LOCAL, F_NO_AUTOTUNE = 1, 2, 4, 8
-F_BUFFER_CROSS, F_LOCAL_HEAP, F_IDLE_PRUNE = 16, 32, 64
+F_BUFFER_CROSS, F_LOCAL_HEAP, F_IDLE_PRUNE, F_PRUNE_NO_HUBS = 16, 32, 64, 128
 
 ERRORS = {
     0: "SSSP_OK", -1: "SSSP_ERR_ARG", -2: "SSSP_ERR_SOURCE", -3: "SSSP_ERR_CSR",
@@ -57,14 +57,14 @@ class Opts(ctypes.Structure):
 
 
 STATS_FIELDS = ["edges_relaxed", "label_updates", "cross_updates", "vertices_expanded",
-                "batches", "edges_pruned", "wedges"]
+                "batches", "edges_pruned", "wedges", "hub_pruned"]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("num_partitions", ctypes.c_int32),
                 ("delta_bits", ctypes.c_uint64)] + \
                [(f, ctypes.c_uint64) for f in STATS_FIELDS] + \
-               [("reserved", ctypes.c_uint64 * 6)]
+               [("reserved", ctypes.c_uint64 * 5)]
 
 
 _lib = None
@@ -153,11 +153,12 @@ def _csr(row_ptr, col, w) -> CSR:
 
 def make_opts(delta=0.0, num_partitions=0, wg_size=0, num_workgroups=0, max_rounds=0,
               validate=True, sync=False, local=False, no_autotune=False, events=None,
-              lag=0, buffer_cross=False, local_heap=False, idle_prune=False) -> Opts:
+              lag=0, buffer_cross=False, local_heap=False, idle_prune=False,
+              hubs=True) -> Opts:
     flags = (F_VALIDATE if validate else 0) | (F_SYNC if sync else 0) | \
             (F_PRUNE_LOCAL if local else 0) | (F_NO_AUTOTUNE if no_autotune else 0) | \
             (F_BUFFER_CROSS if buffer_cross else 0) | (F_LOCAL_HEAP if local_heap else 0) | \
-            (F_IDLE_PRUNE if idle_prune else 0)
+            (F_IDLE_PRUNE if idle_prune else 0) | (0 if hubs else F_PRUNE_NO_HUBS)
     o = Opts()
     o.delta = float(delta)
     o.num_partitions = int(num_partitions)
@@ -199,13 +200,14 @@ class StatsBuffer:
 
 # --------------------------------------------------------------------- prune
 def prune(row_ptr, col, w, *, compact=True, local=False, num_partitions=0, validate=True,
-          sync=True, stats=None, events=None):
+          sync=True, stats=None, events=None, hubs=True):
     """Trishla pruning.  Returns keep (uint8[m]); with compact=True also
     (row_ptr', col', w', edge_map) of the kept arcs (trimmed, which reads the
-    kept count back to the host)."""
+    kept count back to the host).  hubs=False skips the hub pass (same
+    result)."""
     g = _csr(row_ptr, col, w)
     o = make_opts(num_partitions=num_partitions, validate=validate, sync=sync, local=local,
-                  events=events)
+                  events=events, hubs=hubs)
     dev = col.device
     L = lib()
     outs = (None,) * 4

@@ -254,3 +254,72 @@ def test_sparse_rows_and_wide_heads_keep_masks():
     ref = oracle.trishla(g.row_ptr, g.col, g.w)
     assert (ref == 0).sum() > 100
     assert np.array_equal(gpu_keep(g), ref)
+
+
+# ----------------------------------------------------------------- hub pass
+def _hub_cases():
+    yield "tiny", tiny_graph(7, n=60, m=400, wmax=6)
+    yield "tiny_loops_dupes", tiny_graph(8, n=40, m=600, wmax=3, zero=True, loops=True)
+    yield "c1", gen.uniform(4096, 32768, seed=1)
+    yield "rmat13", gen.rmat(13, 12)
+    yield "rmat15_wide", gen.rmat(15, 5, wlo=1, whi=1_000_000)
+    yield "rmat12_zero_costs", gen.rmat(12, 6, wlo=0, whi=3)
+    yield "rmat12_constant", gen.rmat(12, 9, wlo=7, whi=7)
+
+
+@pytest.mark.parametrize("case", [c for c, _ in _hub_cases()])
+def test_hub_pass_keeps_the_deletion_set(case):
+    """The hub pass (the 64 best middles tried for every arc first, from
+    8-bit cost codes that are exact for spans up to 254 and upper bounds
+    beyond) deletes only arcs of the deletion set, and with the scans gives
+    the oracle's keep mask, the same as the scans alone: tiny graphs (where
+    every middle is a hub) with self-loops, parallel arcs and zero costs,
+    C1, R-MAT with exact and with coarse codes, constant costs."""
+    g = dict(_hub_cases())[case]
+    ref = oracle.trishla(g.row_ptr, g.col, g.w)
+    S = sssp_mod()
+    rp, c, w = dev(g)
+    st = S.StatsBuffer.new("cuda")
+    with_hubs = S.prune(rp, c, w, compact=False, stats=st).cpu().numpy()
+    s = st.read()
+    without = S.prune(rp, c, w, compact=False, hubs=False).cpu().numpy()
+    assert np.array_equal(with_hubs, ref)
+    assert np.array_equal(without, ref)
+    assert s["status"] == 0 and s["edges_pruned"] == int((ref == 0).sum())
+    assert s["hub_pruned"] <= s["edges_pruned"]
+
+
+def test_hub_pass_counts():
+    """On R-MAT the hub pass deletes most of the deleted arcs, the scans
+    examine fewer list entries, and without it nothing is counted."""
+    g = gen.rmat(16, 13)
+    ref = oracle.trishla(g.row_ptr, g.col, g.w)
+    S = sssp_mod()
+    rp, c, w = dev(g)
+    st, st0 = S.StatsBuffer.new("cuda"), S.StatsBuffer.new("cuda")
+    k1 = S.prune(rp, c, w, compact=False, stats=st).cpu().numpy()
+    k0 = S.prune(rp, c, w, compact=False, stats=st0, hubs=False).cpu().numpy()
+    assert np.array_equal(k1, ref) and np.array_equal(k0, ref)
+    s, s0 = st.read(), st0.read()
+    assert s0["hub_pruned"] == 0
+    assert s["edges_pruned"] == s0["edges_pruned"] == int((ref == 0).sum())
+    assert s["hub_pruned"] > s["edges_pruned"] // 2
+    assert s["wedges"] < s0["wedges"]
+
+
+def test_hub_pass_off_for_fp32_and_local():
+    """fp32 costs and LOCAL scope skip the hub pass (exact keep masks, no
+    hub deletions counted)."""
+    S = sssp_mod()
+    g = gen.rmat(12, 3, weight="f32", wlo=0.5, whi=1.5)
+    rp, c, w = dev(g)
+    st = S.StatsBuffer.new("cuda")
+    keep = S.prune(rp, c, w, compact=False, stats=st).cpu().numpy()
+    assert np.array_equal(keep, oracle.trishla(g.row_ptr, g.col, g.w))
+    assert st.read()["hub_pruned"] == 0
+    g = gen.rmat(12, 4)
+    rp, c, w = dev(g)
+    st = S.StatsBuffer.new("cuda")
+    keep = S.prune(rp, c, w, compact=False, stats=st, local=True, num_partitions=8).cpu().numpy()
+    assert np.array_equal(keep, oracle.trishla(g.row_ptr, g.col, g.w, True, 8))
+    assert st.read()["hub_pruned"] == 0
