@@ -5,7 +5,8 @@
 // unbounded bucket; then P around its default; then lag; then the workgroup
 // size; then the grid size).  Each setting is timed from five sources and
 // scored by the median time; a setting replaces the best so far only when
-// it is more than 3% faster.
+// its median is more than 3% faster and it is not slower from the caller's
+// own source.
 //
 // The bucket width trades the two effects the paper's related-work section
 // describes for delta-stepping: a wide bucket exposes more parallel work per
@@ -277,9 +278,10 @@ extern "C" int sssp_autotune(const sssp_csr *g, int32_t source, void *dist_scrat
     std::vector<float> sorted = per;
     std::sort(sorted.begin(), sorted.end());
     const float score = sorted[ns / 2];
-    // a new setting must win by more than run-to-run noise (3%): the
-    // defaults, tried first, stay unless something is clearly faster
-    if (!found || score < 0.97f * best_score) {
+    // a new setting must win the median by more than run-to-run noise (3%)
+    // and must not be slower from the caller's own source: the defaults,
+    // tried first, stay unless something is clearly faster
+    if (!found || (score < 0.97f * best_score && per[0] <= best_per[0])) {
       best_score = score;
       best_per = per;
       cur = cand;
