@@ -262,7 +262,8 @@ __global__ void k_tb_zero(TbArgs a) {
 // rows in LDS and finds the row of each arc by a binary search there, so
 // the stores are coalesced whatever the row lengths.  A tile spanning more
 // than TL_ROWS rows (long runs of empty rows) searches row_ptr in place.
-constexpr int TL_BS = 256, TL_E = 4096, TL_ROWS = 2048;
+constexpr int TL_BS = 256, TL_E = 4096, TL_ROWS = 2048, TL_PT = TL_E / TL_BS;
+static_assert(TL_PT % 4 == 0, "whole int4 stores");
 
 __device__ __forceinline__ int tl_tiles(const TbArgs &a) {
   return (int)(((long long)a.m + TL_E - 1) / TL_E);
@@ -292,14 +293,44 @@ __global__ __launch_bounds__(TL_BS) void k_tb_tails(TbArgs a) {
     if (in_lds)
       for (int r = threadIdx.x; r <= cnt; r += TL_BS) s_rp[r] = a.row_ptr[u0 + r];
     __syncthreads();
-    for (int e = e0 + threadIdx.x; e < e1; e += TL_BS) {
-      int lo = 0, hi = cnt - 1;  // last row r with row_ptr[u0 + r] <= e
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if ((in_lds ? s_rp[mid] : a.row_ptr[u0 + mid]) <= e) lo = mid;
-        else hi = mid - 1;
+    if (in_lds) {
+      // TL_PT consecutive arcs per thread: one search for the first, then a
+      // walk over the row bounds (at most cnt steps per thread)
+      const int ea = e0 + threadIdx.x * TL_PT;
+      if (ea < e1) {
+        int lo = 0, hi = cnt - 1;  // last row r with row_ptr[u0 + r] <= ea
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_rp[mid] <= ea) lo = mid;
+          else hi = mid - 1;
+        }
+        int out[TL_PT];
+#pragma unroll
+        for (int i = 0; i < TL_PT; i++) {
+          while (lo + 1 < cnt && s_rp[lo + 1] <= ea + i) lo++;
+          out[i] = u0 + lo;
+        }
+        if (ea + TL_PT <= e1) {
+          int4 *d = reinterpret_cast<int4 *>(a.src + ea);
+#pragma unroll
+          for (int i = 0; i < TL_PT / 4; i++)
+            d[i] = make_int4(out[4 * i], out[4 * i + 1], out[4 * i + 2], out[4 * i + 3]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < TL_PT; i++)
+            if (ea + i < e1) a.src[ea + i] = out[i];
+        }
       }
-      a.src[e] = u0 + lo;
+    } else {
+      for (int e = e0 + threadIdx.x; e < e1; e += TL_BS) {
+        int lo = 0, hi = cnt - 1;  // last row r with row_ptr[u0 + r] <= e
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (a.row_ptr[u0 + mid] <= e) lo = mid;
+          else hi = mid - 1;
+        }
+        a.src[e] = u0 + lo;
+      }
     }
     __syncthreads();
   }
@@ -1849,7 +1880,7 @@ int launch_prune(const sssp_csr &g, int local, bool hubs, int bsize, uint8_t *ke
   if (launch_excl_scan(a.ccnt, n, a.cb, tmp, st) != hipSuccess) return SSSP_ERR_HIP;
   if (m > 0) hipLaunchKernelGGL(k_csc_place, dim3(chunks), dim3(C_BS), 0, st, a);
   if (a.hubs) {  // before the cost order, which moves the CSC entries
-    hipLaunchKernelGGL(k_hub_hist, dim3(grid_cus), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_hub_hist, dim3(grid_cus * 4), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_hub_take, dim3(blocks), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_hub_tables, dim3(64, HUB_K), dim3(256), 0, st, a);
   }
