@@ -1727,7 +1727,7 @@ void launch_resident(K kernel, int bs, int grid_cus, const TbArgs &a, hipStream_
 // (default priority, non-blocking streams) and kept for the life of the
 // process.  A call holds side_mutex() from its first fork to its last join,
 // so each wait pairs with that call's own record.
-constexpr int SIDE_STREAMS = 3, SIDE_EVENTS = 6;
+constexpr int SIDE_STREAMS = 3, SIDE_EVENTS = 8;
 struct SideStreams {
   hipStream_t s[SIDE_STREAMS] = {};
   hipEvent_t ev[SIDE_EVENTS] = {};
@@ -1878,12 +1878,6 @@ int launch_prune(const sssp_csr &g, int local, bool hubs, int bsize, uint8_t *ke
     hipLaunchKernelGGL(k_csc_count, dim3(chunks), dim3(C_BS), 0, st, a);
   }
   if (launch_excl_scan(a.ccnt, n, a.cb, tmp, st) != hipSuccess) return SSSP_ERR_HIP;
-  if (m > 0) hipLaunchKernelGGL(k_csc_place, dim3(chunks), dim3(C_BS), 0, st, a);
-  if (a.hubs) {  // before the cost order, which moves the CSC entries
-    hipLaunchKernelGGL(k_hub_hist, dim3(grid_cus * 4), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_hub_take, dim3(blocks), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_hub_tables, dim3(64, HUB_K), dim3(256), 0, st, a);
-  }
   // Side streams, unless st is being captured (then everything stays on st).
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cap) != hipSuccess) return SSSP_ERR_HIP;
@@ -1893,9 +1887,30 @@ int launch_prune(const sssp_csr &g, int local, bool hubs, int bsize, uint8_t *ke
     side_lock = std::unique_lock<std::mutex>(side_mutex());
     if (!(side = side_streams())) return SSSP_ERR_HIP;
   }
-  // The cost order (lists of at most SORT_MAX entries) runs beside the work
-  // estimate, the classification and the global tables (lists longer than
-  // HV_TCAP only): they touch disjoint data, and the scans need both.
+  // The u-side work estimate and the hub selection need only the CSR and
+  // the column sizes: they run beside the CSC placement (which charges the
+  // x-side work to the other half of `work`).
+  hipStream_t ast = st;
+  if (side) {
+    if (hipEventRecord(side->ev[6], st) != hipSuccess ||
+        hipStreamWaitEvent(side->s[1], side->ev[6], 0) != hipSuccess)
+      return SSSP_ERR_HIP;
+    ast = side->s[1];
+  }
+  hipLaunchKernelGGL(k_tb_work, dim3(blocks), dim3(256), 0, ast, a);
+  if (a.hubs) {
+    hipLaunchKernelGGL(k_hub_hist, dim3(grid_cus * 4), dim3(256), 0, ast, a);
+    hipLaunchKernelGGL(k_hub_take, dim3(blocks), dim3(256), 0, ast, a);
+  }
+  if (side && hipEventRecord(side->ev[7], ast) != hipSuccess) return SSSP_ERR_HIP;
+  if (m > 0) hipLaunchKernelGGL(k_csc_place, dim3(chunks), dim3(C_BS), 0, st, a);
+  if (side && hipStreamWaitEvent(st, side->ev[7], 0) != hipSuccess) return SSSP_ERR_HIP;
+  // the hubs' code rows read their CSC columns: after the placement, before
+  // the cost order moves the entries
+  if (a.hubs) hipLaunchKernelGGL(k_hub_tables, dim3(64, HUB_K), dim3(256), 0, st, a);
+  // The cost order (lists of at most SORT_MAX entries) runs beside the
+  // classification and the global tables (lists longer than HV_TCAP only):
+  // they touch disjoint data, and the scans need both.
   hipStream_t ost = st;
   if (side) {
     if (hipEventRecord(side->ev[0], st) != hipSuccess ||
@@ -1908,7 +1923,6 @@ int launch_prune(const sssp_csr &g, int local, bool hubs, int bsize, uint8_t *ke
   hipLaunchKernelGGL(k_tb_sort_small, dim3(blocks), dim3(256), 0, ost, a);
   hipLaunchKernelGGL(k_tb_sort_mid, dim3(grid_cus * 8), dim3(ORD_BS), 0, ost, a);
   if (side && hipEventRecord(side->ev[1], ost) != hipSuccess) return SSSP_ERR_HIP;
-  hipLaunchKernelGGL(k_tb_work, dim3(blocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_tb_classify, dim3(grid_cus * 2), dim3(CLF_BS), 0, st, a);
   hipLaunchKernelGGL(k_tb_gclear, dim3(blocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_tb_gtab, dim3(grid_cus, 16), dim3(256), 0, st, a);
