@@ -126,7 +126,7 @@ enum {
      together with the two modes above (SSSP_ERR_ARG). */
   SSSP_F_IDLE_PRUNE = 1u << 6,
   /* sssp_prune: skip the hub pass (the arcs are tested through the
-     HUB_K = 64 vertices with the most two-arc paths first, with integer
+     32 vertices with the most two-arc paths first, with integer
      costs, GLOBAL scope and n <= 2^23); the result is the same, only the
      time changes.  For comparisons. */
   SSSP_F_PRUNE_NO_HUBS = 1u << 7

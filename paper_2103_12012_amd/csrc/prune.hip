@@ -338,7 +338,7 @@ __global__ __launch_bounds__(TL_BS) void k_tb_tails(TbArgs a) {
 
 // ------------------------------------------------------------------ hubs
 // Hub pass.  Most deleted arcs have a witness through one of a few
-// high-degree middles (on R-MAT 20, 66% of them through the 64 vertices
+// high-degree middles (on R-MAT 20, 59% of them through the 32 vertices
 // with the most two-arc paths), which a scan reaches only after the
 // cheaper entries of its list.  So every arc about to be scanned first
 // tries those HUB_K middles at once: row u of `hin` holds the code of the
