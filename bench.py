@@ -631,6 +631,26 @@ def bench_ablation(steps):
         out[name] = {"solve_ms": float(np.median(ts)), "edges_relaxed": st["edges_relaxed"],
                      "label_updates": st["label_updates"],
                      "vertices_expanded": st["vertices_expanded"], "batches": st["batches"]}
+    # Trishla with and without its hub pass (the same deletion set): the scan
+    # phase (library events) and the whole prune call (stream events)
+    for name, hubs in (("prune_with_hub_pass", True), ("prune_without_hub_pass", False)):
+        scan, whole = [], []
+        for _ in range(max(3, steps)):
+            st_buf = sssp.StatsBuffer.new("cuda")
+            e = ev.pair()
+            t0e = torch.cuda.Event(enable_timing=True)
+            t1e = torch.cuda.Event(enable_timing=True)
+            t0e.record()
+            sssp.prune(rp, c, w, compact=False, num_partitions=256, validate=False, sync=False,
+                       stats=st_buf, events=e, hubs=hubs)
+            t1e.record()
+            torch.cuda.synchronize()
+            scan.append(ev.ms(e))
+            whole.append(t0e.elapsed_time(t1e))
+        pst = st_buf.read()
+        out[name] = {"scan_ms": float(np.median(scan)), "prune_call_ms": float(np.median(whole)),
+                     "entries_examined": pst["wedges"], "hub_pass_deleted": pst["hub_pruned"],
+                     "edges_pruned": pst["edges_pruned"]}
     # idle-time LOCAL pruning inside the solve, on the unpruned graph (no
     # separate Trishla phase), against the plain solve of the unpruned graph
     for name, kw in (("unpruned_plain", {}), ("unpruned_idle_prune", dict(idle_prune=True))):
