@@ -17,8 +17,9 @@
 //  * the scan of an arc stops at its first witness.
 //
 // The scans advance in rounds: each live arc takes a chunk of its list
-// (Q_D0 entries, doubling every round), the chunks of all live arcs of a
-// batch are laid end to end over the lanes, and finished arcs drop out.
+// (Q_D0 entries, doubling every round), the chunks of all live arcs are
+// laid end to end over the lanes, and a finished arc's slot takes the next
+// arc of the work item (one wave per light owner: batches of 64 arcs).
 //
 //  * arcs with |N_out(u)| <= |N_in(x)| ("x-side") are grouped by x and use
 //    the table of N_in(x); the others ("u-side") are grouped by u and use
@@ -1371,7 +1372,7 @@ __global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
   static_assert(QN <= BS && QN <= 1024 && (long long)QN * Q_DMAX < (1 << LIVE_SH), "packing");
   __shared__ TbHeavy<SLOTS, QN, NM, FSH> H;
   __shared__ int s_ws[BS / WAVE + 1];
-  __shared__ int s_t;
+  __shared__ int s_t, s_next, s_cmax[2];
   if (*a.status) return;
   const int tid = threadIdx.x;
   const HList &hl = a.hl[TIER];
@@ -1431,46 +1432,67 @@ __global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
       tval = H.val;
     }
     const int tmask = (1 << tbits) - 1;
-    // this item's share of the owner's arcs, in batches of QN
+    // This item's share of the owner's arcs.  Slot tid (< QN) holds one arc
+    // at a time; at the start of every round a slot whose arc is done (or
+    // that holds none) takes the next arc of the item, so rounds stay full
+    // instead of draining a fixed batch.  Each arc's chunks double from Q_D0.
     const int p0 = (int)((long long)o.llen * k / ni);
     const int p1 = (int)((long long)o.llen * (k + 1) / ni);
-    for (int r0 = p0; r0 < p1; r0 += QN) {
-      const int nq = min(QN, p1 - r0);
-      int cur = 0;  // next list position of this thread's arc
-      if (tid < nq) {
-        const Query q = make_query(a, o, o.lbeg + r0 + tid);
-        cur = q.beg;
-        H.qlim[tid] = q.beg + q.len;
-        H.qrec[tid] = make_int4(q.other, (int)q.stop, (int)q.W, q.eid);
-        hubdel += q.hub;
+    if (tid == 0) {
+      s_next = p0;
+      s_cmax[0] = 0;
+      s_cmax[1] = 0;
+    }
+    __syncthreads();
+    int cur = 0, D = Q_D0;  // this slot's next list position and chunk
+    bool has = false;       // this slot holds an arc
+    for (int round = 0;; round++) {
+      if (tid < QN && (!has || cur >= H.qlim[tid])) {
+        const int pos = atomicAdd(&s_next, 1);
+        has = pos < p1;
+        if (has) {
+          const Query q = make_query(a, o, o.lbeg + pos);
+          cur = q.beg;
+          D = Q_D0;
+          H.qlim[tid] = q.beg + q.len;
+          H.qrec[tid] = make_int4(q.other, (int)q.stop, (int)q.W, q.eid);
+          hubdel += q.hub;
+        }
+      }
+      const int c = has ? max(0, min(D, H.qlim[tid] - cur)) : 0;
+      const int cm = wave_max(c);
+      if (lane_id() == 0 && cm > 0) atomicMax(&s_cmax[round & 1], cm);
+      int packed;
+      // one barrier: s_ws is next written after this round's last barrier
+      const int run = block_excl_scan1<BS>(live_pack(c), s_ws, &packed);
+      const int tot = packed & ((1 << LIVE_SH) - 1);
+      if (tot == 0) {
+        // every held arc is done: stop once the item has no arc left
+        const bool more = s_next < p1;
+        if (tid == 0) s_cmax[(round + 1) & 1] = 0;
+        __syncthreads();  // s_next is read by all before the next refill
+        if (!more) break;
+        continue;
+      }
+      const int gshift = mark_shift(tot, NM, s_cmax[round & 1]);
+      if (c > 0) {
+        const int sl = run >> LIVE_SH, off = run & ((1 << LIVE_SH) - 1);
+        H.srec[sl] = make_int2(tid, cur - off);
+        H.soff[sl] = off;
+        put_marks(H.mark, gshift, sl, off, c);
+      }
+      if (tid == 0) {
+        H.soff[packed >> LIVE_SH] = tot;
+        H.mark[((tot - 1) >> gshift) + 1] = (packed >> LIVE_SH) - 1;
+        s_cmax[(round + 1) & 1] = 0;  // the next round's maximum
       }
       __syncthreads();
-      for (int D = Q_D0;; D = min(2 * D, Q_DMAX)) {
-        int c = 0;
-        if (tid < nq) c = max(0, min(D, H.qlim[tid] - cur));
-        int packed;
-        // one barrier: s_ws is next written after this round's last barrier
-        const int run = block_excl_scan1<BS>(live_pack(c), s_ws, &packed);
-        const int tot = packed & ((1 << LIVE_SH) - 1);
-        if (tot == 0) break;
-        const int gshift = mark_shift(tot, NM, D);
-        if (c > 0) {
-          const int sl = run >> LIVE_SH, off = run & ((1 << LIVE_SH) - 1);
-          H.srec[sl] = make_int2(tid, cur - off);
-          H.soff[sl] = off;
-          put_marks(H.mark, gshift, sl, off, c);
-        }
-        if (tid == 0) {
-          H.soff[packed >> LIVE_SH] = tot;
-          H.mark[((tot - 1) >> gshift) + 1] = (packed >> LIVE_SH) - 1;
-        }
-        __syncthreads();
-        scan_entries<WT>(a, o, tid, BS, tot, H.mark, gshift, H.soff, H.srec, H.qlim, H.qrec, tkey,
-                         tval, tmask, tbits, filt, fbits);
-        probes += tid == 0 ? (unsigned long long)tot : 0ull;
-        __syncthreads();
-        cur += c;
-      }
+      scan_entries<WT>(a, o, tid, BS, tot, H.mark, gshift, H.soff, H.srec, H.qlim, H.qrec, tkey,
+                       tval, tmask, tbits, filt, fbits);
+      probes += tid == 0 ? (unsigned long long)tot : 0ull;
+      __syncthreads();
+      cur += c;
+      D = min(2 * D, Q_DMAX);
     }
     __syncthreads();
   }
