@@ -68,6 +68,7 @@ constexpr int TK_SORT_SHORT = NTIER, TK_SORT_LONG = NTIER + 1, TK_LIGHT = NTIER 
 constexpr int HM_BS = 256;
 constexpr int HM_Q = 256;            // medium: arcs staged per batch
 constexpr int HM_MARKS = 1024;       // medium: slot marks of a round
+constexpr int HS_MARKS = 512;        // tier 0: fewer marks, so 8 workgroups fit a CU's LDS
 constexpr int HM_FSH = 3;            // 256-thread tiers: filter bits per table slot, log2
 constexpr int HV_TCAP = 8192;        // big heavy owner: longest list in an LDS table
 constexpr int HV_SLOTS = 16384;
@@ -1412,12 +1413,12 @@ struct TbLight {         // one per wave
   int32_t mark[LT_MARKS + 1];
 };
 
-// Waves per SIMD the register budget must allow.  Tier 0's LDS fits 7
-// workgroups per CU and the light kernel's 8: without a bound the compiler
-// takes 84 and 78 VGPRs (5 and 6 waves); bounded it takes 70 (two spills)
+// Waves per SIMD the register budget must allow.  The LDS of tier 0 and of
+// the light kernel fits 8 workgroups per CU: without a bound the compiler
+// takes 84 and 78 VGPRs (5 and 6 waves); bounded it takes 62 (two spills)
 // and 63, and the scans are latency bound, so the extra waves win.  The
 // other tiers are held to fewer waves by their LDS tables.
-constexpr int tier_waves(int tier) { return tier == 0 ? 7 : 1; }
+constexpr int tier_waves(int tier) { return tier == 0 ? 8 : 1; }
 constexpr int LT_WAVES = 8;
 
 // Heavy owners of one tier: workgroup items taken from a ticket counter;
@@ -1851,7 +1852,7 @@ template <int WT>
 hipError_t launch_scan_kernels(const TbArgs &a, int grid_cus, hipStream_t st, SideStreams *d) {
   static_assert(NTIER == 4, "one launch per heavy tier");
   auto k_light = k_tb_light<WT>;
-  auto k_t0 = k_tb_heavy<WT, 0, HM_BS, HS_SLOTS, HM_Q, HM_MARKS, HM_FSH>;
+  auto k_t0 = k_tb_heavy<WT, 0, HM_BS, HS_SLOTS, HM_Q, HS_MARKS, HM_FSH>;
   auto k_t1 = k_tb_heavy<WT, 1, HM_BS, HM1_SLOTS, HM_Q, HM_MARKS, HM_FSH>;
   auto k_t2 = k_tb_heavy<WT, 2, HM_BS, HM_SLOTS, HM_Q, HM_MARKS, HM_FSH>;
   auto k_big = k_tb_heavy<WT, T_BIG, TB_BS, HV_SLOTS, HV_Q, HV_MARKS, HV_FSH>;
