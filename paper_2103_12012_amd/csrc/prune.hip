@@ -66,6 +66,7 @@ constexpr int HM_SLOTS = 4096;
 // and the light owners
 constexpr int TK_SORT_SHORT = NTIER, TK_SORT_LONG = NTIER + 1, TK_LIGHT = NTIER + 2;
 constexpr int HM_BS = 256;
+constexpr int H2_BS = 512;           // tier 2: two slot-less threads per arc slot
 constexpr int HM_Q = 256;            // medium: arcs staged per batch
 constexpr int HM_MARKS = 1024;       // medium: slot marks of a round
 constexpr int HS_MARKS = 512;        // tier 0: fewer marks, so 8 workgroups fit a CU's LDS
@@ -1416,9 +1417,11 @@ struct TbLight {         // one per wave
 // Waves per SIMD the register budget must allow.  The LDS of tier 0 and of
 // the light kernel fits 8 workgroups per CU: without a bound the compiler
 // takes 84 and 78 VGPRs (5 and 6 waves); bounded it takes 62 (two spills)
-// and 63, and the scans are latency bound, so the extra waves win.  The
-// other tiers are held to fewer waves by their LDS tables.
-constexpr int tier_waves(int tier) { return tier == 0 ? 8 : 1; }
+// and 63, and the scans are latency bound, so the extra waves win.  Tier
+// 2's 48 KB table fits 3 workgroups per CU, so it runs 512 threads (with
+// 256 arc slots) at up to 6 waves per SIMD (75 VGPRs).  Tier 1 and the big
+// tier are held to their waves by their LDS.
+constexpr int tier_waves(int tier) { return tier == 0 ? 8 : (tier == 2 ? 6 : 1); }
 constexpr int LT_WAVES = 8;
 
 // Heavy owners of one tier: workgroup items taken from a ticket counter;
@@ -1854,13 +1857,13 @@ hipError_t launch_scan_kernels(const TbArgs &a, int grid_cus, hipStream_t st, Si
   auto k_light = k_tb_light<WT>;
   auto k_t0 = k_tb_heavy<WT, 0, HM_BS, HS_SLOTS, HM_Q, HS_MARKS, HM_FSH>;
   auto k_t1 = k_tb_heavy<WT, 1, HM_BS, HM1_SLOTS, HM_Q, HM_MARKS, HM_FSH>;
-  auto k_t2 = k_tb_heavy<WT, 2, HM_BS, HM_SLOTS, HM_Q, HM_MARKS, HM_FSH>;
+  auto k_t2 = k_tb_heavy<WT, 2, H2_BS, HM_SLOTS, HM_Q, HM_MARKS, HM_FSH>;
   auto k_big = k_tb_heavy<WT, T_BIG, TB_BS, HV_SLOTS, HV_Q, HV_MARKS, HV_FSH>;
   if (!d) {
     launch_resident(k_light, LT_BS, grid_cus, a, st);
     launch_resident(k_t0, HM_BS, grid_cus, a, st);
     launch_resident(k_t1, HM_BS, grid_cus, a, st);
-    launch_resident(k_t2, HM_BS, grid_cus, a, st);
+    launch_resident(k_t2, H2_BS, grid_cus, a, st);
     launch_resident(k_big, TB_BS, grid_cus, a, st);
     return hipSuccess;
   }
@@ -1869,7 +1872,7 @@ hipError_t launch_scan_kernels(const TbArgs &a, int grid_cus, hipStream_t st, Si
   for (int i = 0; i < SIDE_STREAMS; i++)
     if ((err = hipStreamWaitEvent(d->s[i], d->ev[2], 0)) != hipSuccess) return err;
   launch_resident(k_big, TB_BS, grid_cus, a, d->s[0]);
-  launch_resident(k_t2, HM_BS, grid_cus, a, d->s[1]);
+  launch_resident(k_t2, H2_BS, grid_cus, a, d->s[1]);
   launch_resident(k_t1, HM_BS, grid_cus, a, d->s[2]);
   launch_resident(k_light, LT_BS, grid_cus, a, st);
   launch_resident(k_t0, HM_BS, grid_cus, a, st);
