@@ -13,9 +13,7 @@
 //
 //  * every list of SORT_MIN+1 .. SORT_MAX entries is sorted by cost, so the
 //    scan of an arc of cost W stops at the first entry with cost >= W (no
-//    later entry can be the cheap half of a detour), and the costs sampled
-//    at QS - 1 evenly spaced positions of the list bound where that entry
-//    can be before the scan starts, and
+//    later entry can be the cheap half of a detour), and
 //  * the scan of an arc stops at its first witness.
 //
 // The scans advance in rounds: each live arc takes a chunk of its list
@@ -66,10 +64,8 @@ constexpr int HM_SLOTS = 4096;
 // and the light owners
 constexpr int TK_SORT_SHORT = NTIER, TK_SORT_LONG = NTIER + 1, TK_LIGHT = NTIER + 2;
 constexpr int HM_BS = 256;
-constexpr int H2_BS = 512;           // tier 2: two slot-less threads per arc slot
 constexpr int HM_Q = 256;            // medium: arcs staged per batch
 constexpr int HM_MARKS = 1024;       // medium: slot marks of a round
-constexpr int HS_MARKS = 512;        // tier 0: fewer marks, so 8 workgroups fit a CU's LDS
 constexpr int HM_FSH = 3;            // 256-thread tiers: filter bits per table slot, log2
 constexpr int HV_TCAP = 8192;        // big heavy owner: longest list in an LDS table
 constexpr int HV_SLOTS = 16384;
@@ -141,7 +137,7 @@ struct TbArgs {
   int2 *cyw;        // m: CSC entries (tail, cost); sorted lists by cost
   int32_t *ceid;    // m: CSC -> CSR edge id (moves with cyw)
   int2 *rs;         // m: CSR rows as (head, cost); sorted lists by cost
-  int4 *lmeta;      // 2n: ordered list metadata (see ListMeta)
+  int2 *lmeta;      // 2n: (least cost, bucket shift) of an ordered list; shift -1: unordered
   int32_t *sl;      // 2n: lists to sort, short ones from the front, long
                     //     ones (> SORT_WAVE entries) from the back
   int32_t *work;    // 2n: probes of owner i (i < n: in-table of i; else out-table of i-n)
@@ -741,32 +737,10 @@ __global__ __launch_bounds__(C_BS) void k_csc_place(TbArgs a) {
 // buckets of width 2^s above its least cost lo, s the least shift that
 // fits its cost span: an exact cost order when the span is below NBK (any
 // integer costs up to 255 apart), bucket order otherwise.  Costs compare
-// as uint32 bits (nonnegative floats order the same way).  lmeta keeps,
-// per ordered list, lo, s and the buckets found at QS - 1 evenly spaced
-// positions, for the scans' stop rule and scan limit; the order of equal
+// as uint32 bits (nonnegative floats order the same way).  lmeta keeps
+// (lo, s) per ordered list for the scans' stop rule; the order of equal
 // buckets is arbitrary.
 constexpr int NBK = 256;
-// lmeta of a list: x = lo (uint32 bits); byte 0 of y = s (0xFF: unordered
-// list); byte k (1 <= k < QS) of (y, z, w) = the bucket of the entry at
-// position floor(len * k / QS).  Buckets never decrease along an ordered
-// list, so if sample k lies above bucket b, no entry from floor(len*k/QS)
-// on is in bucket b or below.
-constexpr int QS = 12;
-__device__ __forceinline__ int meta_shift(int4 lm) { return lm.y & 0xFF; }
-__device__ __forceinline__ uint32_t meta_sample(int4 lm, int k) {
-  const int word = k < 4 ? lm.y : (k < 8 ? lm.z : lm.w);
-  return ((uint32_t)word >> (8 * (k & 3))) & 0xFFu;
-}
-// Entry pos (0 <= pos < len, len > QS) of bucket b: if pos is a sampled
-// position, record b as its sample (every sample is written exactly once).
-__device__ __forceinline__ void put_sample(uint8_t *samp, int len, int pos, int b) {
-  const int k = (QS * pos + len - 1) / len;  // the least k with len * k / QS >= pos
-  if (k >= 1 && k < QS && len * k / QS == pos) samp[k] = (uint8_t)b;
-}
-__device__ __forceinline__ int4 pack_meta(uint32_t lo, int s, const uint8_t *samp) {
-  const uint32_t *w = reinterpret_cast<const uint32_t *>(samp);
-  return make_int4((int)lo, (int)((w[0] & ~0xFFu) | (uint32_t)s), (int)w[1], (int)w[2]);
-}
 constexpr int ORD_BS = 256;          // workgroup of a long list (one bucket per thread)
 constexpr int ORD_R = SORT_MAX / ORD_BS;
 
@@ -837,7 +811,7 @@ __global__ __launch_bounds__(CLS_BS) void k_tb_sort_class(TbArgs a) {
       const uint32_t c = sorted_len(len) ? (len > SORT_WAVE ? 2u : 1u) : 0u;
       cls |= c << (2 * k);
       cnt += c == 1u ? 1 : (c == 2u ? 1 << 16 : 0);
-      a.lmeta[i] = make_int4(0, -1, 0, 0);  // unordered unless ordered below
+      a.lmeta[i] = make_int2(0, -1);  // unordered unless ordered below
     }
     int tot;
     const int pre = block_excl_scan1<CLS_BS>(cnt, s_ws, &tot);
@@ -861,8 +835,7 @@ __global__ __launch_bounds__(CLS_BS) void k_tb_sort_class(TbArgs a) {
 // One wave per short queued list (SORT_MIN < length <= SORT_WAVE): the
 // entries stay in registers, the bucket counters in the wave's LDS.
 template <int R>
-__device__ __forceinline__ void wave_order(const TbArgs &a, int li, const SortSeg &g, int *cnt,
-                                           uint8_t *samp) {
+__device__ __forceinline__ void wave_order(const TbArgs &a, int li, const SortSeg &g, int *cnt) {
   const int lane = lane_id();
   int2 yw[R];
   int pay[R], bk[R], rk[R];
@@ -907,31 +880,24 @@ __device__ __forceinline__ void wave_order(const TbArgs &a, int li, const SortSe
   wave_sync();
 #pragma unroll
   for (int r = 0; r < R; r++)
-    if (lane + WAVE * r < g.len) {
-      const int pos = cnt[bk[r]] + rk[r];
-      ord_put(a, g, g.beg + pos, yw[r], pay[r]);
-      put_sample(samp, g.len, pos, bk[r]);
-    }
-  wave_sync();
-  if (lane == 0) a.lmeta[li] = pack_meta(lo, s, samp);
+    if (lane + WAVE * r < g.len) ord_put(a, g, g.beg + cnt[bk[r]] + rk[r], yw[r], pay[r]);
+  if (lane == 0) a.lmeta[li] = make_int2((int)lo, s);
   wave_sync();
 }
 
 __global__ __launch_bounds__(256) void k_tb_sort_small(TbArgs a) {
   __shared__ int s_cnt[256 / WAVE][NBK];
-  __shared__ uint32_t s_samp[256 / WAVE][QS / 4];
   if (*a.status) return;
   int *cnt = s_cnt[threadIdx.x / WAVE];
-  uint8_t *samp = reinterpret_cast<uint8_t *>(s_samp[threadIdx.x / WAVE]);
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int nwaves = gridDim.x * blockDim.x / WAVE;
   const int ns = a.tickets[TK_SORT_SHORT];
   for (int j = wave; j < ns; j += nwaves) {
     const int li = a.sl[j];
     const SortSeg g = sort_seg(a, li);
-    if (g.len <= WAVE) wave_order<1>(a, li, g, cnt, samp);
-    else if (g.len <= 2 * WAVE) wave_order<2>(a, li, g, cnt, samp);
-    else wave_order<4>(a, li, g, cnt, samp);
+    if (g.len <= WAVE) wave_order<1>(a, li, g, cnt);
+    else if (g.len <= 2 * WAVE) wave_order<2>(a, li, g, cnt);
+    else wave_order<4>(a, li, g, cnt);
   }
 }
 
@@ -940,7 +906,6 @@ __global__ __launch_bounds__(256) void k_tb_sort_small(TbArgs a) {
 __global__ __launch_bounds__(ORD_BS) void k_tb_sort_mid(TbArgs a) {
   static_assert(ORD_BS == NBK, "one bucket per thread");
   __shared__ int s_cnt[NBK];
-  __shared__ uint32_t s_samp[QS / 4];
   __shared__ uint32_t s_lo[ORD_BS / WAVE], s_hi[ORD_BS / WAVE];
   __shared__ int s_ws[ORD_BS / WAVE + 1];
   if (*a.status) return;
@@ -988,16 +953,10 @@ __global__ __launch_bounds__(ORD_BS) void k_tb_sort_mid(TbArgs a) {
     const int off = block_excl_scan<ORD_BS>(s_cnt[tid], s_ws, &tot);
     s_cnt[tid] = off;
     __syncthreads();
-    uint8_t *samp = reinterpret_cast<uint8_t *>(s_samp);
 #pragma unroll
     for (int r = 0; r < ORD_R; r++)
-      if (tid + ORD_BS * r < g.len) {
-        const int pos = s_cnt[bk[r]] + rk[r];
-        ord_put(a, g, g.beg + pos, yw[r], pay[r]);
-        put_sample(samp, g.len, pos, bk[r]);
-      }
-    __syncthreads();
-    if (tid == 0) a.lmeta[li] = pack_meta(lo, s, samp);
+      if (tid + ORD_BS * r < g.len) ord_put(a, g, g.beg + s_cnt[bk[r]] + rk[r], yw[r], pay[r]);
+    if (tid == 0) a.lmeta[li] = make_int2((int)lo, s);
     __syncthreads();
   }
 }
@@ -1208,31 +1167,22 @@ struct Query {
 };
 
 // Stop bound of a scan of a list with metadata lm (its lmeta entry) for an
-// arc of cost W, and its scan limit.  Only entries of cost <= W - 1 (as
-// uint32 bits: the next lower float for fp32) can be the cheap half of a
-// detour; in an ordered list every entry after one in a higher bucket than
-// W - 1's costs more, so an entry of cost above the last cost of that
-// bucket ends the scan, and the first sampled position in a higher bucket
-// bounds the scan up front (len is lowered to it).  Unordered lists never
-// stop; a list whose least cost is >= W is not scanned at all (len = 0).
-__device__ __forceinline__ uint32_t scan_stop(int4 lm, uint32_t W, int &len) {
-  const int s = meta_shift(lm);
-  if (len == 0 || s == 0xFF) return 0xFFFFFFFFu;
+// arc of cost W.  Only entries of
+// cost <= W - 1 (as uint32 bits: the next lower float for fp32) can be the
+// cheap half of a detour; in an ordered list every entry after one in a
+// higher bucket than W - 1's costs more, so an entry of cost above the last
+// cost of that bucket ends the scan.  Unordered lists never stop; a list
+// whose least cost is >= W is not scanned at all (len = 0).
+__device__ __forceinline__ uint32_t scan_stop(int2 lm, uint32_t W, int &len) {
+  if (len == 0 || lm.y < 0) return 0xFFFFFFFFu;
   const uint32_t lo = (uint32_t)lm.x;
   if (W <= lo) {
     len = 0;
     return 0u;
   }
-  const uint32_t bw = ((W - 1u) - lo) >> s;  // the last bucket that can help
-  if (bw < (uint32_t)(NBK - 1)) {
-    int kk = QS;
-#pragma unroll
-    for (int k = QS - 1; k >= 1; k--)
-      if (meta_sample(lm, k) > bw) kk = k;
-    len = len * kk / QS;
-  }
   const unsigned long long last =
-      (unsigned long long)lo + (((unsigned long long)bw + 1ull) << s) - 1ull;
+      (unsigned long long)lo + (((unsigned long long)(((W - 1u) - lo) >> lm.y) + 1ull) << lm.y) -
+      1ull;
   return last >= 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)last;
 }
 
@@ -1242,7 +1192,7 @@ __device__ __forceinline__ Query make_query(const TbArgs &a, const Owner &o, int
     const int2 uw = a.cyw[p];
     const int u = uw.x;
     const int rs = a.row_ptr[u], ou = a.row_ptr[u + 1] - rs;
-    const int4 lm = a.lmeta[u];  // loaded with the row bounds, not after them
+    const int2 lm = a.lmeta[u];  // loaded with the row bounds, not after them
     q.beg = rs;
     q.len = ou <= o.llen ? ou : 0;
     q.W = (uint32_t)uw.y;
@@ -1252,7 +1202,7 @@ __device__ __forceinline__ Query make_query(const TbArgs &a, const Owner &o, int
   } else {  // arc (u = t -> x): scan N_in(x) when |N_in(x)| < |N_out(u)|
     const int x = a.col[p];
     const int cs = cbeg(a, x), ix = clen(a, x);
-    const int4 lm = a.lmeta[a.n + x];
+    const int2 lm = a.lmeta[a.n + x];
     q.beg = cs;
     q.len = o.llen <= ix ? 0 : ix;
     q.W = a.w[p];
@@ -1414,22 +1364,11 @@ struct TbLight {         // one per wave
   int32_t mark[LT_MARKS + 1];
 };
 
-// Waves per SIMD the register budget must allow.  The LDS of tier 0 and of
-// the light kernel fits 8 workgroups per CU: without a bound the compiler
-// takes 84 and 78 VGPRs (5 and 6 waves); bounded it takes 62 (two spills)
-// and 63, and the scans are latency bound, so the extra waves win.  Tier
-// 2's 48 KB table fits 3 workgroups per CU, so it runs 512 threads (with
-// 256 arc slots) at up to 6 waves per SIMD (75 VGPRs).  Tier 1 and the big
-// tier are held to their waves by their LDS.
-constexpr int tier_waves(int tier) { return tier == 0 ? 8 : (tier == 2 ? 6 : 1); }
-constexpr int LT_WAVES = 8;
-
 // Heavy owners of one tier: workgroup items taken from a ticket counter;
 // the owner's table is in LDS (SLOTS slots) or, for the longest lists of
 // the big tier, in global memory.
 template <int WT, int TIER, int BS, int SLOTS, int QN, int NM, int FSH>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(tier_waves(TIER))))
-void k_tb_heavy(TbArgs a) {
+__global__ __launch_bounds__(BS) void k_tb_heavy(TbArgs a) {
   static_assert(QN <= BS && QN <= 1024 && (long long)QN * Q_DMAX < (1 << LIVE_SH), "packing");
   __shared__ TbHeavy<SLOTS, QN, NM, FSH> H;
   __shared__ int s_ws[BS / WAVE + 1];
@@ -1566,8 +1505,7 @@ void k_tb_heavy(TbArgs a) {
 
 // Light owners: one wave per owner of llist, a private LDS table.
 template <int WT>
-__global__ __launch_bounds__(LT_BS) __attribute__((amdgpu_waves_per_eu(LT_WAVES)))
-void k_tb_light(TbArgs a) {
+__global__ __launch_bounds__(LT_BS) void k_tb_light(TbArgs a) {
   __shared__ TbLight sw[LT_BS / WAVE];
   if (*a.status) return;
   const int lane = lane_id();
@@ -1764,7 +1702,7 @@ PruneLayout prune_layout(int n, int m, bool compact) {
   L.cyw = take(8ull * m);
   L.ceid = take(4ull * m);
   L.rs = take(8ull * m);
-  L.lmeta = take(16 * n2);
+  L.lmeta = take(8 * n2);
   L.sl = take(4 * n2);
   L.llist = take(4 * n2);
   L.work = take(4 * n2);
@@ -1855,15 +1793,15 @@ template <int WT>
 hipError_t launch_scan_kernels(const TbArgs &a, int grid_cus, hipStream_t st, SideStreams *d) {
   static_assert(NTIER == 4, "one launch per heavy tier");
   auto k_light = k_tb_light<WT>;
-  auto k_t0 = k_tb_heavy<WT, 0, HM_BS, HS_SLOTS, HM_Q, HS_MARKS, HM_FSH>;
+  auto k_t0 = k_tb_heavy<WT, 0, HM_BS, HS_SLOTS, HM_Q, HM_MARKS, HM_FSH>;
   auto k_t1 = k_tb_heavy<WT, 1, HM_BS, HM1_SLOTS, HM_Q, HM_MARKS, HM_FSH>;
-  auto k_t2 = k_tb_heavy<WT, 2, H2_BS, HM_SLOTS, HM_Q, HM_MARKS, HM_FSH>;
+  auto k_t2 = k_tb_heavy<WT, 2, HM_BS, HM_SLOTS, HM_Q, HM_MARKS, HM_FSH>;
   auto k_big = k_tb_heavy<WT, T_BIG, TB_BS, HV_SLOTS, HV_Q, HV_MARKS, HV_FSH>;
   if (!d) {
     launch_resident(k_light, LT_BS, grid_cus, a, st);
     launch_resident(k_t0, HM_BS, grid_cus, a, st);
     launch_resident(k_t1, HM_BS, grid_cus, a, st);
-    launch_resident(k_t2, H2_BS, grid_cus, a, st);
+    launch_resident(k_t2, HM_BS, grid_cus, a, st);
     launch_resident(k_big, TB_BS, grid_cus, a, st);
     return hipSuccess;
   }
@@ -1872,7 +1810,7 @@ hipError_t launch_scan_kernels(const TbArgs &a, int grid_cus, hipStream_t st, Si
   for (int i = 0; i < SIDE_STREAMS; i++)
     if ((err = hipStreamWaitEvent(d->s[i], d->ev[2], 0)) != hipSuccess) return err;
   launch_resident(k_big, TB_BS, grid_cus, a, d->s[0]);
-  launch_resident(k_t2, H2_BS, grid_cus, a, d->s[1]);
+  launch_resident(k_t2, HM_BS, grid_cus, a, d->s[1]);
   launch_resident(k_t1, HM_BS, grid_cus, a, d->s[2]);
   launch_resident(k_light, LT_BS, grid_cus, a, st);
   launch_resident(k_t0, HM_BS, grid_cus, a, st);
@@ -1916,7 +1854,7 @@ int launch_prune(const sssp_csr &g, int local, bool hubs, int bsize, uint8_t *ke
   a.cyw = reinterpret_cast<int2 *>(ws + L.cyw);
   a.ceid = reinterpret_cast<int32_t *>(ws + L.ceid);
   a.rs = reinterpret_cast<int2 *>(ws + L.rs);
-  a.lmeta = reinterpret_cast<int4 *>(ws + L.lmeta);
+  a.lmeta = reinterpret_cast<int2 *>(ws + L.lmeta);
   a.sl = reinterpret_cast<int32_t *>(ws + L.sl);
   a.llist = reinterpret_cast<int32_t *>(ws + L.llist);
   a.work = reinterpret_cast<int32_t *>(ws + L.work);
