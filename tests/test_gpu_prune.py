@@ -144,6 +144,34 @@ def test_pruned_solve_equals_unpruned(scale, seed):
                             ref)
 
 
+@pytest.mark.parametrize("byte", [0x5A, 0xFF])
+def test_stale_workspace_contents_do_not_matter(byte):
+    """Workspaces and outputs come from torch.empty, so they hold whatever an
+    earlier allocation left.  Fill the allocator's cached memory with a byte
+    pattern (0x5A: large positive int32 values; 0xFF: -1 everywhere), then
+    prune with compaction and solve the pruned graph (buffered updates too):
+    the keep mask and the results equal the oracle's."""
+    torch.cuda.synchronize()
+    junk = torch.full((1 << 30,), byte, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    del junk  # back to the caching allocator with its contents
+    g = gen.rmat(16, 41)
+    S = sssp_mod()
+    rp, c, w = dev(g)
+    keep, (prp, pc, pw, emap) = S.prune(rp, c, w, num_partitions=16)
+    assert np.array_equal(keep.cpu().numpy(), oracle.trishla(g.row_ptr, g.col, g.w))
+    emap = emap.cpu().numpy()
+    s = int(gen.random_sources(g, 1, 41)[0])
+    ref = oracle.solve(g.row_ptr, g.col, g.w, s)
+    for kw in ({}, {"buffer_cross": True}):
+        solver = S.Solver(prp, pc, pw, num_partitions=16, **kw)
+        dist, pred, pe = solver(s, sync=True)
+        pe = pe.cpu().numpy()
+        pe = np.where(pe >= 0, emap[np.maximum(pe, 0)], -1)
+        assert_solve_parity(g, s, (dist.cpu().numpy().view(np.uint32), pred.cpu().numpy(), pe),
+                            ref)
+
+
 def test_rmat20_keep_mask_full_size():
     g = gen.rmat(20, 20)
     assert np.array_equal(gpu_keep(g, num_partitions=256), oracle.trishla(g.row_ptr, g.col, g.w))
