@@ -53,3 +53,16 @@ def tiny_graph(seed, n=None, m=None, wmax=5, zero=True, loops=True):
         u, v = u[keep], v[keep]
     w = rng.integers(0 if zero else 1, wmax + 1, size=u.shape[0]).astype(np.uint32)
     return gen.from_arcs(n, u, v, w)
+
+
+def poison_cached_memory(byte, nbytes=1 << 30):
+    """Leave `nbytes` of device memory filled with `byte` in torch's caching
+    allocator, so the next allocations (workspaces, outputs) start with that
+    pattern instead of fresh zeroed pages."""
+    import torch
+
+    torch.cuda.synchronize()
+    junk = torch.full((nbytes,), byte, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    del junk
+

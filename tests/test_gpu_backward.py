@@ -8,7 +8,7 @@ import torch
 
 import oracle
 from paper_2103_12012_amd import gen
-from helpers import dev, sssp_mod
+from helpers import dev, poison_cached_memory, sssp_mod
 
 pytestmark = pytest.mark.gpu
 
@@ -41,6 +41,19 @@ def test_forward_and_gradient_match_oracle(scale, seed):
     pe_ref, _ = oracle.pred(g.row_ptr, g.col, g.w, s, dref)
     gref = oracle.grad(g.row_ptr, s, pe_ref, gv)
     np.testing.assert_allclose(gw, gref, rtol=1e-4, atol=1e-4)
+
+
+@pytest.mark.parametrize("byte", [0x5A, 0xFF])
+def test_gradient_with_stale_workspace_contents(byte):
+    """Forward and backward give the oracle's distances and gradient when
+    their workspaces and outputs start with a stale byte pattern."""
+    g, s, gv = setup(13, 15)
+    poison_cached_memory(byte)
+    d, gw, loss = gpu_grad(g, s, gv)
+    dref = oracle.sssp(g.row_ptr, g.col, g.w, s)
+    assert np.array_equal(d.view(np.uint32), dref.view(np.uint32))
+    pe_ref, _ = oracle.pred(g.row_ptr, g.col, g.w, s, dref)
+    np.testing.assert_allclose(gw, oracle.grad(g.row_ptr, s, pe_ref, gv), rtol=1e-4, atol=1e-4)
 
 
 def test_gradient_matches_finite_differences_scale10():

@@ -7,7 +7,7 @@ import torch
 
 import oracle
 from paper_2103_12012_amd import gen
-from helpers import assert_solve_parity, dev, sssp_mod
+from helpers import assert_solve_parity, dev, poison_cached_memory, sssp_mod
 
 pytestmark = pytest.mark.gpu
 
@@ -56,6 +56,18 @@ def test_batch_mixed_sizes_and_tiny():
     ss = [0, 5, int(gen.random_sources(graphs[2], 1, 1)[0]), 299, 0]
     S = sssp_mod()
     check(graphs, sg, ss, S.solve_batch([dev(g) for g in graphs], sg, ss))
+
+
+@pytest.mark.parametrize("byte", [0x5A, 0xFF])
+def test_batch_with_stale_workspace_contents(byte):
+    """The batched launch's workspace and outputs start with whatever the
+    allocator's cached memory held (a byte pattern here); results still
+    equal the oracle's."""
+    graphs, sg, ss = make_batch(6, 9, 13, seed=5)
+    S = sssp_mod()
+    dg = [dev(g) for g in graphs]
+    poison_cached_memory(byte)
+    check(graphs, sg, ss, S.solve_batch(dg, sg, ss))
 
 
 def test_batch_hip_graph_replays():

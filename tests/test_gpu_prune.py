@@ -11,7 +11,8 @@ import torch
 
 import oracle
 from paper_2103_12012_amd import gen
-from helpers import assert_solve_parity, dev, gpu_solve, sssp_mod, tiny_graph
+from helpers import (assert_solve_parity, dev, gpu_solve, poison_cached_memory, sssp_mod,
+                     tiny_graph)
 
 pytestmark = pytest.mark.gpu
 
@@ -151,10 +152,7 @@ def test_stale_workspace_contents_do_not_matter(byte):
     pattern (0x5A: large positive int32 values; 0xFF: -1 everywhere), then
     prune with compaction and solve the pruned graph (buffered updates too):
     the keep mask and the results equal the oracle's."""
-    torch.cuda.synchronize()
-    junk = torch.full((1 << 30,), byte, dtype=torch.uint8, device="cuda")
-    torch.cuda.synchronize()
-    del junk  # back to the caching allocator with its contents
+    poison_cached_memory(byte)
     g = gen.rmat(16, 41)
     S = sssp_mod()
     rp, c, w = dev(g)
