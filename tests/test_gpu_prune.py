@@ -119,6 +119,31 @@ def test_rmat_local_scope_subset():
         assert np.all(kl >= kg)
 
 
+@pytest.mark.parametrize("P", [7, 64, 1024])
+def test_rmat16_local_scope_keep_masks(P):
+    """LOCAL scope (a witness only through a middle in the tail's own
+    partition) at R-MAT 16 over a few partition counts, bit-exact."""
+    g = gen.rmat(16, 51)
+    ref = oracle.trishla(g.row_ptr, g.col, g.w, True, P)
+    assert np.array_equal(gpu_keep(g, local=True, num_partitions=P), ref)
+
+
+def test_fp32_rmat16_keep_mask_and_compaction():
+    """fp32 costs at R-MAT 16: keep mask, compacted arrays (costs carried
+    bit for bit) and edge map against the oracle."""
+    g = gen.rmat(16, 52, weight="f32", wlo=0.5, whi=1.5)
+    rp, c, w = dev(g)
+    keep, (prp, pc, pw, emap) = sssp_mod().prune(rp, c, w)
+    ref = oracle.trishla(g.row_ptr, g.col, g.w)
+    assert np.array_equal(keep.cpu().numpy(), ref)
+    kept = np.nonzero(ref)[0]
+    assert np.array_equal(emap.cpu().numpy(), kept)
+    assert np.array_equal(pc.cpu().numpy(), g.col[kept])
+    assert np.array_equal(pw.cpu().numpy().view(np.uint32), g.w[kept].view(np.uint32))
+    cnt = np.bincount(g.src()[kept], minlength=g.n)
+    assert np.array_equal(prp.cpu().numpy(), np.concatenate([[0], np.cumsum(cnt)]))
+
+
 def test_fp32_keep_mask():
     g = gen.rmat(11, 9, weight="f32", wlo=0.5, whi=1.5)
     assert np.array_equal(gpu_keep(g), oracle.trishla(g.row_ptr, g.col, g.w))
