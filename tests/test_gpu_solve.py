@@ -93,6 +93,20 @@ def test_grid_small(R, C):
     assert_solve_parity(g, 0, gpu_solve(g, 0, num_partitions=max(1, g.n // 512)))
 
 
+@pytest.mark.parametrize("opts", [dict(), dict(delta=1, num_partitions=7),
+                                  dict(delta=-1, num_partitions=64), dict(buffer_cross=True),
+                                  dict(local_heap=True)])
+def test_rmat_mostly_zero_costs(opts):
+    """R-MAT 14 with costs in {0, 1, 2}: long zero-cost paths and zero-cost
+    cycles, so most labels tie and the predecessor rule (the smallest arc id
+    among tight arcs) decides; bit-exact against the oracle in every mode."""
+    g0 = gen.rmat(14, 61)
+    w = np.random.default_rng(61).choice(np.array([0, 0, 0, 1, 2], np.uint32), size=g0.m)
+    g = gen.CSR(g0.n, g0.row_ptr, g0.col, w)
+    s = int(gen.random_sources(g, 1, 61)[0])
+    assert_solve_parity(g, s, gpu_solve(g, s, **opts))
+
+
 def test_isolated_source_and_empty_graph():
     g = gen.from_arcs(5, [], [], np.zeros(0, np.uint32))
     dist, pred, pe = gpu_solve(g, 3)
